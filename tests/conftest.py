@@ -1,0 +1,25 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _cpu_libs():
+    """The generator and the oracle are plain C built with gcc; build them if
+    they are missing (they are test inputs and test infrastructure)."""
+    import synth
+    import oracle
+    if not os.path.exists(synth._LIB_PATH):
+        synth.build()
+    if not os.path.exists(oracle._LIB_PATH):
+        oracle.build()
