@@ -1,0 +1,290 @@
+/*
+ * resoct.h — C ABI of the residency-octree hot path on MI355X (gfx950).
+ *
+ * Implements ray-guided, mixed-resolution, multi-channel direct volume ray
+ * casting over a residency octree (Herzberger et al., "Residency Octree: A
+ * Hybrid Approach for Scalable Web-Based Multi-Volume Rendering",
+ * arXiv 2309.04393), split along the paper's division of work: the CPU
+ * dispatches rendering and memory-management commands, forwards requests
+ * and uploads bricks; the GPU renders, records cache misses under a global
+ * per-frame limit, and keeps page tables and the residency octree up to
+ * date (Sec. 4 System Overview).
+ *
+ * Conventions
+ *  - Every call returns ro_status: 0 on success, < 0 on error; ro_last_error()
+ *    returns a thread-local message for the last failing call.  Arguments are
+ *    validated before any work is enqueued, and a failing call leaves every
+ *    state unchanged.  Device faults surface as RO_E_DEVICE at the next call
+ *    that synchronises, carrying the HIP error string.
+ *  - Handles are opaque, host-side and not thread-safe: one owner thread per
+ *    handle.  Calls on a handle must use one stream (or be ordered by the
+ *    caller across streams).
+ *  - `stream` arguments are hipStream_t values passed as void* (NULL = the
+ *    null stream).  Work is enqueued asynchronously on that stream except
+ *    where a call says it synchronises.
+ *  - All device memory is owned by the caller: sizes come from the *_query
+ *    calls, pointers are handed over at create time, and the library never
+ *    frees them.  Destroy calls free host handle memory only.  Device buffers
+ *    must be 256-byte aligned.
+ *  - Brick IDs (Sec. 6): 32-bit, page-table ID c*k + l in bits 24-31 (c =
+ *    cache channel, l = level, k = number of levels), brick z in bits 16-23,
+ *    y in 8-15, x in 0-7.  Hence at most 256 bricks per axis per level and
+ *    m*k <= 256 page tables.
+ *  - Coordinates: L0 voxel i of an axis covers [i, i+1) and has its centre
+ *    at i + 1/2; world position = L0 coordinate * spacing.  Level l scales
+ *    each axis by a power-of-two factor f_l (axis a is halved from level l-1
+ *    to l iff its spacing at l-1 is below twice the smallest spacing at l-1;
+ *    halved dims are ceil(n/2)).  Brick b of level l holds level voxels
+ *    [b*B, (b+1)*B) per axis and is stored with a one-voxel halo of its
+ *    same-level neighbours, clamp-replicated at the level's borders:
+ *    (B+2)^3 voxels, x fastest.
+ */
+#ifndef RESOCT_H
+#define RESOCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ro_status;
+#define RO_OK 0
+#define RO_E_ARG (-1)      /* invalid argument */
+#define RO_E_CAPACITY (-2) /* a size exceeds what IDs, buffers or tables can hold */
+#define RO_E_NOMEM (-3)    /* host allocation failed */
+#define RO_E_DEVICE (-4)   /* HIP error (launch, copy or an earlier asynchronous fault) */
+#define RO_E_STATE (-5)    /* call not valid in the handle's current state */
+
+#define RO_MAX_CHANNELS 16
+#define RO_MAX_LEVELS 16
+#define RO_MAX_DEPTH 20
+
+typedef struct ro_volume ro_volume;
+typedef struct ro_cache ro_cache;
+typedef struct ro_octree ro_octree;
+
+/* ---------------------------------------------------------------- volume */
+
+/* Bricked multi-resolution multi-channel volume (Sec. 3 "Brick hierarchy";
+ * Sec. 4 "Multi-channel data").  All channels share one brick size. */
+typedef struct {
+    int32_t dims[3];         /* L0 voxels per axis, each >= 1 */
+    double spacing[3];       /* world units per L0 voxel, > 0 */
+    int32_t n_channels;      /* m: channels referenced by cache and tree, 1..16 */
+    int32_t bytes_per_voxel; /* 1 (uint8) or 2 (uint16); values are unsigned raw */
+    int32_t brick;           /* B: interior brick edge, power of two in [4, 128] */
+    int32_t n_levels;        /* k: resolution levels, 1..16 */
+} ro_volume_desc;
+
+/* Validates and derives the level schedule.  RO_E_CAPACITY when a level has
+ * more than 256 bricks on an axis or m*k > 256 (brick-ID capacity, Sec. 6). */
+ro_status ro_volume_create(const ro_volume_desc *desc, ro_volume **out);
+void ro_volume_destroy(ro_volume *v);
+
+/* Level geometry: dims_out[l*3+a], factor_out[l*3+a] (L0 voxels per level
+ * voxel) and bricks_out[l*3+a] for l < k.  Any pointer may be NULL. */
+ro_status ro_volume_levels(const ro_volume *v, int32_t *dims_out, int32_t *factor_out,
+                           int32_t *bricks_out);
+
+/* Total bricks over all channels and levels (= page-table entries). */
+ro_status ro_volume_brick_count(const ro_volume *v, uint64_t *count);
+
+/* Brick ID encode / decode (Sec. 6).  RO_E_ARG for out-of-range fields. */
+ro_status ro_brick_id_encode(const ro_volume *v, uint32_t c, uint32_t l, const uint32_t b[3],
+                             uint32_t *id);
+ro_status ro_brick_id_decode(const ro_volume *v, uint32_t id, uint32_t *c, uint32_t *l,
+                             uint32_t b[3]);
+
+/* ----------------------------------------------------------------- cache */
+
+/* Brick cache and multi-channel multi-resolution page tables (Sec. 5.1):
+ * one pool of equal-size slots shared by all channels and levels. */
+typedef struct {
+    uint32_t n_slots;   /* S >= 1 */
+    uint32_t max_batch; /* most uploads per ro_stream_bricks call, 1..8192 */
+} ro_cache_desc;
+
+/* Device buffers of a cache, each caller-allocated with the queried size.
+ *  slots       S * slot_stride bytes: brick voxels, (B+2)^3 per slot
+ *  page_table  one uint32 per brick: slot or 0xFFFFFFFF (not resident)
+ *  counters    one uint32 per brick: cache-miss counts of the current frame;
+ *              must be zero at create (the create call clears it)
+ *  slot_brick  one uint32 per slot: brick index held, 0xFFFFFFFF if free
+ *  stamps      one uint32 per slot: frame of last use or upload (LRU)
+ *  seqs        one uint32 per slot: upload sequence number (LRU tie-break)
+ *  scratch     work space of the streaming and compaction kernels */
+typedef struct {
+    size_t slots, page_table, counters, slot_brick, stamps, seqs, scratch;
+    size_t slot_stride; /* bytes per slot (and per staged brick), multiple of 256 */
+} ro_cache_sizes;
+
+typedef struct {
+    void *slots;
+    uint32_t *page_table, *counters, *slot_brick, *stamps, *seqs;
+    void *scratch;
+} ro_cache_buffers;
+
+ro_status ro_cache_query(const ro_volume *v, const ro_cache_desc *desc, ro_cache_sizes *out);
+
+/* Clears page table, counters, slot map, stamps and seqs on `stream`. */
+ro_status ro_cache_create(const ro_volume *v, const ro_cache_desc *desc,
+                          const ro_cache_buffers *bufs, void *stream, ro_cache **out);
+void ro_cache_destroy(ro_cache *c);
+
+/* Upload one batch of bricks in frame `frame` (Sec. 5.3 "Updating residency
+ * information", "LRU cache eviction").  ids_host[n] are brick IDs in the
+ * policy's order; staged_dev holds n bricks, brick i at
+ * staged_dev + i * slot_stride, halo included.  Slots are assigned on the
+ * GPU: free slots first in ascending order, then resident slots in ascending
+ * (stamp, seq) order, never a slot whose stamp equals `frame` (used this
+ * frame).  An ID resident at the start of the batch, or repeated earlier in
+ * it, gets flag 2 and its slot's stamp is set to `frame`; uploads that find
+ * no eligible slot get flag 0; inserted ones flag 1 (inserted_host[n]).
+ * Evicted and inserted bricks are recorded for ro_update_residency.
+ * Synchronises on `stream` before returning (flags are host memory).
+ * n <= max_batch; frame < 0xFFFFFFFF. */
+ro_status ro_stream_bricks(ro_cache *c, uint32_t frame, uint32_t n, const uint32_t *ids_host,
+                           const void *staged_dev, uint8_t *inserted_host, void *stream);
+
+/* Cache-miss readback (Sec. 4: global limit on recorded misses per frame).
+ * Compacts the per-brick counters into (id, count) pairs in ascending ID
+ * order, returns at most `cap` of them, the number of distinct requested
+ * bricks (*n_unique, may exceed cap) and the sum of all counts
+ * (*total_missing), then zeroes the counters.  Synchronises. */
+ro_status ro_read_requests(ro_cache *c, uint32_t cap, uint32_t *ids_host, uint32_t *counts_host,
+                           uint32_t *n_unique, uint64_t *total_missing, void *stream);
+
+/* Slots read during frame `frame` (stamp == frame), ascending, at most cap;
+ * *n_out receives the full count.  Synchronises. */
+ro_status ro_read_usage(ro_cache *c, uint32_t frame, uint32_t cap, uint32_t *slots_host,
+                        uint32_t *n_out, void *stream);
+
+/* Copy of the host mirror of the page table: brick index -> slot
+ * (0xFFFFFFFF when not resident), `count` entries from ro_volume_brick_count. */
+ro_status ro_cache_page_table_host(const ro_cache *c, uint32_t *out, uint64_t count);
+
+/* ---------------------------------------------------------------- octree */
+
+/* Residency octree (Sec. 5.2): a full pointerless tree over the L0 domain
+ * padded to a power of two number of leaves per axis.  Axis a needs s_a
+ * splits (leaf_a * 2^s_a >= dims_a) and takes them at the last s_a of the
+ * `depth` subdivision levels; node size at level d is
+ * leaf_a << min(s_a, depth - d).  Leaf edges must be powers of two that
+ * divide B, so a leaf lies inside exactly one brick of every level.  Each
+ * node stores per channel the metadata [min, max] (uint16 each, packed
+ * min | max << 16) and the mask of levels in which it is partially mapped
+ * (uint16). */
+typedef struct {
+    int32_t leaf[3];     /* leaf edge in L0 voxels, powers of two dividing B */
+    int32_t depth;       /* subdivision levels below the root, <= 20 */
+    int32_t start_level; /* level where traversal starts each time a ray enters a leaf */
+} ro_octree_desc;
+
+/*  node_meta   n_nodes * m uint32 (min | max << 16)
+ *  node_mask   n_nodes * m uint16
+ *  node_flags  n_nodes bytes (propagation work flags)
+ *  scratch     leaf-update work list */
+typedef struct {
+    size_t node_meta, node_mask, node_flags, scratch;
+    uint64_t n_nodes, n_leaves;
+    int32_t leaf_grid[3]; /* leaves per axis (padded) */
+} ro_octree_sizes;
+
+typedef struct {
+    uint32_t *node_meta;
+    uint16_t *node_mask;
+    uint8_t *node_flags;
+    void *scratch;
+} ro_octree_buffers;
+
+ro_status ro_octree_query(const ro_volume *v, const ro_octree_desc *desc, ro_octree_sizes *out);
+
+/* Clears metadata (to [0, 0]), masks and flags.  The octree refers to the
+ * cache's page tables; destroy it before the cache. */
+ro_status ro_octree_create(ro_cache *c, const ro_octree_desc *desc,
+                           const ro_octree_buffers *bufs, void *stream, ro_octree **out);
+void ro_octree_destroy(ro_octree *t);
+
+/* Leaf metadata of one channel from the data server (Sec. 4; Sec. 5.3
+ * "Updating culling information"): leaf_minmax_dev[n_leaves][2] uint16
+ * (min, max) over the padded leaf grid, x fastest.  Must be conservative
+ * for every L0 voxel within one voxel of the leaf.  Inner nodes then get the
+ * min of their children's minima and the max of their maxima. */
+ro_status ro_octree_set_leaf_metadata(ro_octree *t, uint32_t channel,
+                                      const uint16_t *leaf_minmax_dev, void *stream);
+
+/* Residency update for the bricks inserted or evicted since the last call
+ * (Sec. 5.3): each leaf overlapping such a brick gets bit l of its channel's
+ * mask set iff the level-l brick containing it is resident; then every
+ * inner node whose children changed gets the OR of its children, level by
+ * level, stopping where nothing changed. */
+ro_status ro_update_residency(ro_octree *t, void *stream);
+
+/* From-scratch recomputation of every mask from the page tables. */
+ro_status ro_rebuild_residency(ro_octree *t, void *stream);
+
+/* ---------------------------------------------------------------- render */
+
+#define RO_PROJ_ORTHO 0
+#define RO_PROJ_PERSP 1
+
+#define RO_RENDER_NO_SKIP 1u /* evaluate every sample (results are identical) */
+#define RO_RENDER_AOV 2u     /* write per-pixel per-level sample counts to aov_dev */
+
+/* One frame (Sec. 6.1, Alg. 1; Sec. 6.2).  Pixel (i, j), row 0 at the top,
+ * has a = (2i+1-W)/W, b = (H-2j-1)/H.  Orthographic: origin
+ * eye + a*tx*right + b*ty*up, direction forward.  Perspective: origin eye,
+ * direction normalize(forward + a*tx*right + b*ty*up).  Samples at
+ * t_k = k*step along the ray (world units, k = 0, 1, ...), those outside
+ * the volume are void.  For every sample and visible channel:
+ *  - a leaf whose metadata make the channel's transfer function zero over
+ *    every table entry reachable from [min, max] contributes nothing and
+ *    requests nothing;
+ *  - desired level l* = clamp(#{l >= 1 : t >= D_l}, lod_lo, lod_hi) with
+ *    D_l = s_l / (lod_bias * 2 ty / H), s_l the level's x voxel size
+ *    (orthographic views use the pixel size 2 ty / H in place of t * 2ty/H);
+ *  - a missing desired brick adds one to its miss counter, and the finest
+ *    resident level >= l* substitutes (none: the channel contributes
+ *    nothing); every slot read gets its stamp set to `frame`;
+ *  - value = trilinear interpolation in the slot; the transfer function maps
+ *    v to clamp((v - win_lo/256) / ((win_hi - win_lo)/256), 0, 1) * 255
+ *    and interpolates linearly in the channel's 256-entry RGBA table.
+ * Channels mix per sample as alpha = 1 - prod(1 - alpha_c),
+ * colour = alpha * sum(alpha_c rgb_c) / sum(alpha_c); samples composite
+ * front to back (premultiplied), and a ray stops once its opacity reaches
+ * term_alpha.  Empty-space skipping and the traversal start level change no
+ * output. */
+typedef struct {
+    uint32_t frame;     /* frame number written into slot stamps, < 0xFFFFFFFF */
+    int32_t projection; /* RO_PROJ_ORTHO or RO_PROJ_PERSP */
+    double eye[3], forward[3], right[3], up[3];
+    double tx, ty;      /* ortho: half extents (world); perspective: tan of half angles */
+    int32_t width, height;
+    double step;        /* world distance between samples, > 0 */
+    double lod_bias;    /* > 0 */
+    int32_t n_vis;      /* visible channels, 1..m */
+    int32_t vis[RO_MAX_CHANNELS];    /* cache channel of each visible slot, distinct */
+    int32_t lod_lo[RO_MAX_CHANNELS]; /* per visible slot resolution range, lo <= hi < k */
+    int32_t lod_hi[RO_MAX_CHANNELS];
+    uint32_t win_lo[RO_MAX_CHANNELS]; /* window in raw units, 24.8 fixed point, lo < hi */
+    uint32_t win_hi[RO_MAX_CHANNELS];
+    const float *tf_dev;  /* device [n_vis][256][4] RGBA, alpha >= 0 */
+    float term_alpha;     /* in (0, 1] */
+    int32_t start_level;  /* traversal start level (Sec. 6, implementation), -1: the octree's */
+    uint32_t flags;       /* RO_RENDER_* */
+    uint32_t *aov_dev;    /* RO_RENDER_AOV: device [H][W][k] uint32, zeroed by the caller */
+} ro_frame_desc;
+
+/* Renders into rgba_dev[H][W][4] (float, premultiplied) and updates the
+ * miss counters and slot stamps.  Asynchronous. */
+ro_status ro_render(ro_octree *t, const ro_frame_desc *fd, float *rgba_dev, void *stream);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *ro_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

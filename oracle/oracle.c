@@ -491,7 +491,12 @@ int or_render(const or_volume *V, const void *const *lvl, const int32_t *res_slo
             long long pidx = (long long)j * Fr->W + i;
             double o[3], d[3], t0, t1;
             double Cc[3] = {0, 0, 0}, A = 0.0;
-            int pamb = 0, shadow = 0;
+            /* tol: an early-termination decision was within the margin, so a
+             * reduced-precision renderer may have stopped (or not) there:
+             * every later sample's requests and reads are tolerated.
+             * shadow: this oracle has stopped compositing (A >= term) but
+             * keeps walking the ray to collect those tolerated sets. */
+            int pamb = 0, shadow = 0, tol = 0;
             pixel_ray(V, Fr, i, j, o, d);
             if (box_interval(V, o, d, &t0, &t1)) {
                 long long k0 = (long long)floor(t0 / Fr->delta) - 1;
@@ -507,7 +512,7 @@ int or_render(const or_volume *V, const void *const *lvl, const int32_t *res_slo
                         if (fabs(u[a] - nearbyint(u[a])) < AMB_POS) samb = 1;
                     }
                     if (!inside) {
-                        if (samb && !shadow) pamb = 1; /* box decision is close */
+                        if (samb && !tol) pamb = 1; /* box decision is close */
                         continue;
                     }
                     int iu[3] = {(int)floor(u[0]), (int)floor(u[1]), (int)floor(u[2])};
@@ -523,7 +528,7 @@ int or_render(const or_volume *V, const void *const *lvl, const int32_t *res_slo
                             if (fabs(t - Dl[l]) <= 1e-9 * Dl[l]) samb = 1;
                         }
                     }
-                    if (samb && !shadow) { pamb = 1; st_as++; }
+                    if (samb && !tol) { pamb = 1; st_as++; }
                     if (!shadow) st_s++;
                     double prod = 1.0, sa = 0.0, srgb[3] = {0, 0, 0};
                     for (int jv = 0; jv < Fr->nvis; ++jv) {
@@ -538,7 +543,7 @@ int or_render(const or_volume *V, const void *const *lvl, const int32_t *res_slo
                         for (int a = 0; a < 3; ++a) bs[a] = iu[a] / (G.B * G.f[ls][a]);
                         long long want = dense(&G, c, ls, bs[0], bs[1], bs[2]);
                         if (res_slot[want] < 0) {
-                            if (shadow) {
+                            if (tol) {
                                 if (amb_counts) {
 #pragma omp atomic
                                     amb_counts[want]++;
@@ -561,13 +566,14 @@ int or_render(const or_volume *V, const void *const *lvl, const int32_t *res_slo
                             if (res_slot[di] >= 0) { lu = l; slot = res_slot[di]; break; }
                         }
                         if (lu < 0) continue;
-                        if (shadow) {
+                        if (tol) {
                             if (amb_used) __atomic_store_n(&amb_used[slot], 1, __ATOMIC_RELAXED);
-                            continue;
+                            if (shadow) continue;
+                        } else {
+                            if (used) __atomic_store_n(&used[slot], 1, __ATOMIC_RELAXED);
+                            if (aov) aov[pidx * L + lu]++;
+                            st_cs++;
                         }
-                        if (used) __atomic_store_n(&used[slot], 1, __ATOMIC_RELAXED);
-                        if (aov) aov[pidx * L + lu]++;
-                        st_cs++;
                         double q[3];
                         for (int a = 0; a < 3; ++a) q[a] = u[a] / G.f[lu][a];
                         double v = trilinear(V, lvl[c * L + lu], G.dl[lu], q);
@@ -587,12 +593,14 @@ int or_render(const or_volume *V, const void *const *lvl, const int32_t *res_slo
                         for (int k2 = 0; k2 < 3; ++k2) Cs[k2] = as * srgb[k2] / sa;
                     for (int k2 = 0; k2 < 3; ++k2) Cc[k2] += (1.0 - A) * Cs[k2];
                     A += (1.0 - A) * as;
-                    if (fabs(A - Fr->term_alpha) < Fr->term_margin) {
+                    if (!tol && fabs(A - Fr->term_alpha) < Fr->term_margin) {
                         /* a reduced-precision renderer may decide either way here */
                         pamb = 1;
-                        if (A >= Fr->term_alpha) shadow = 1;
-                    } else if (A >= Fr->term_alpha) {
-                        break;
+                        tol = 1;
+                    }
+                    if (A >= Fr->term_alpha) {
+                        if (!tol) break;
+                        shadow = 1;
                     }
                 }
             }

@@ -1,0 +1,495 @@
+// Host side of the C ABI: validation, geometry, handle bookkeeping.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "common.h"
+
+namespace ro {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+ro_status hip_fail(hipError_t e, const char *what) {
+    set_error("HIP error %d (%s) in %s", (int)e, hipGetErrorString(e), what);
+    return RO_E_DEVICE;
+}
+
+static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+static int ilog2(int64_t x) {
+    int r = 0;
+    while ((1ll << r) < x) ++r;
+    return r;
+}
+static bool aligned(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+
+// Level schedule: halve axis a from level l-1 to l iff its spacing at l-1 is
+// below twice the smallest spacing at l-1; halved dims are ceil(n/2).
+static void derive_levels(const ro_volume_desc &d, VolGeo &g) {
+    double s[3] = {d.spacing[0], d.spacing[1], d.spacing[2]};
+    for (int a = 0; a < 3; ++a) {
+        g.ldims[0][a] = d.dims[a];
+        g.lshift[0][a] = 0;
+    }
+    for (int l = 1; l < d.n_levels; ++l) {
+        double mn = std::min(s[0], std::min(s[1], s[2]));
+        bool h[3];
+        for (int a = 0; a < 3; ++a) h[a] = s[a] < 2.0 * mn;
+        for (int a = 0; a < 3; ++a) {
+            g.ldims[l][a] = h[a] ? (g.ldims[l - 1][a] + 1) / 2 : g.ldims[l - 1][a];
+            g.lshift[l][a] = g.lshift[l - 1][a] + (h[a] ? 1 : 0);
+            if (h[a]) s[a] *= 2.0;
+        }
+    }
+}
+
+}  // namespace ro
+
+using namespace ro;
+
+extern "C" const char *ro_last_error(void) { return g_err; }
+
+extern "C" ro_status ro_volume_create(const ro_volume_desc *d, ro_volume **out) {
+    RO_CHECK(d && out, RO_E_ARG, "null argument");
+    for (int a = 0; a < 3; ++a) {
+        RO_CHECK(d->dims[a] >= 1, RO_E_ARG, "dims[%d] = %d must be >= 1", a, d->dims[a]);
+        RO_CHECK(d->spacing[a] > 0.0, RO_E_ARG, "spacing[%d] must be > 0", a);
+    }
+    RO_CHECK(d->n_channels >= 1 && d->n_channels <= kMaxC, RO_E_ARG, "n_channels %d not in 1..%d",
+             d->n_channels, kMaxC);
+    RO_CHECK(d->bytes_per_voxel == 1 || d->bytes_per_voxel == 2, RO_E_ARG,
+             "bytes_per_voxel must be 1 or 2");
+    RO_CHECK(is_pow2(d->brick) && d->brick >= 4 && d->brick <= 128, RO_E_ARG,
+             "brick %d must be a power of two in [4, 128]", d->brick);
+    RO_CHECK(d->n_levels >= 1 && d->n_levels <= kMaxL, RO_E_ARG, "n_levels %d not in 1..%d",
+             d->n_levels, kMaxL);
+    RO_CHECK(d->n_channels * d->n_levels <= 256, RO_E_CAPACITY,
+             "channels x levels = %d exceeds the 8-bit page-table ID", d->n_channels * d->n_levels);
+    VolGeo g;
+    memset(&g, 0, sizeof(g));
+    derive_levels(*d, g);
+    uint64_t per = 0;
+    for (int l = 0; l < d->n_levels; ++l) {
+        for (int a = 0; a < 3; ++a) {
+            g.nb[l][a] = (g.ldims[l][a] + d->brick - 1) / d->brick;
+            RO_CHECK(g.nb[l][a] <= 256, RO_E_CAPACITY,
+                     "level %d has %d bricks on axis %d; brick IDs hold 256", l, g.nb[l][a], a);
+        }
+        g.loff[l] = (uint32_t)per;
+        per += (uint64_t)g.nb[l][0] * g.nb[l][1] * g.nb[l][2];
+    }
+    g.loff[d->n_levels] = (uint32_t)per;
+    RO_CHECK(per * d->n_channels < 0xFFFFFFFFull, RO_E_CAPACITY, "too many bricks");
+    for (int a = 0; a < 3; ++a) {
+        g.dims[a] = d->dims[a];
+        g.spacing[a] = d->spacing[a];
+    }
+    g.m = d->n_channels;
+    g.bpv = d->bytes_per_voxel;
+    g.B = d->brick;
+    g.Blog = ilog2(d->brick);
+    g.E = d->brick + 2;
+    g.L = d->n_levels;
+    g.per_channel = (uint32_t)per;
+    g.total = per * (uint64_t)d->n_channels;
+    uint64_t sb = (uint64_t)g.E * g.E * g.E * g.bpv;
+    g.slot_stride = (uint32_t)((sb + 255) / 256 * 256);
+    ro_volume *v = new (std::nothrow) ro_volume;
+    RO_CHECK(v, RO_E_NOMEM, "out of host memory");
+    v->desc = *d;
+    v->g = g;
+    *out = v;
+    return RO_OK;
+}
+
+extern "C" void ro_volume_destroy(ro_volume *v) { delete v; }
+
+extern "C" ro_status ro_volume_levels(const ro_volume *v, int32_t *dims_out, int32_t *factor_out,
+                                      int32_t *bricks_out) {
+    RO_CHECK(v, RO_E_ARG, "null volume");
+    for (int l = 0; l < v->g.L; ++l)
+        for (int a = 0; a < 3; ++a) {
+            if (dims_out) dims_out[3 * l + a] = v->g.ldims[l][a];
+            if (factor_out) factor_out[3 * l + a] = 1 << v->g.lshift[l][a];
+            if (bricks_out) bricks_out[3 * l + a] = v->g.nb[l][a];
+        }
+    return RO_OK;
+}
+
+extern "C" ro_status ro_volume_brick_count(const ro_volume *v, uint64_t *count) {
+    RO_CHECK(v && count, RO_E_ARG, "null argument");
+    *count = v->g.total;
+    return RO_OK;
+}
+
+extern "C" ro_status ro_brick_id_encode(const ro_volume *v, uint32_t c, uint32_t l,
+                                        const uint32_t b[3], uint32_t *id) {
+    RO_CHECK(v && b && id, RO_E_ARG, "null argument");
+    RO_CHECK(c < (uint32_t)v->g.m && l < (uint32_t)v->g.L, RO_E_ARG, "channel or level out of range");
+    for (int a = 0; a < 3; ++a)
+        RO_CHECK(b[a] < (uint32_t)v->g.nb[l][a], RO_E_ARG, "brick coordinate out of range");
+    *id = ((c * (uint32_t)v->g.L + l) << 24) | (b[2] << 16) | (b[1] << 8) | b[0];
+    return RO_OK;
+}
+
+// Brick ID -> (c, l, b) with range checks; returns false if out of range.
+static bool decode_id(const VolGeo &g, uint32_t id, uint32_t *c, uint32_t *l, uint32_t b[3]) {
+    uint32_t pt = id >> 24;
+    *c = pt / (uint32_t)g.L;
+    *l = pt % (uint32_t)g.L;
+    b[0] = id & 255u;
+    b[1] = (id >> 8) & 255u;
+    b[2] = (id >> 16) & 255u;
+    if (*c >= (uint32_t)g.m) return false;
+    for (int a = 0; a < 3; ++a)
+        if (b[a] >= (uint32_t)g.nb[*l][a]) return false;
+    return true;
+}
+
+extern "C" ro_status ro_brick_id_decode(const ro_volume *v, uint32_t id, uint32_t *c, uint32_t *l,
+                                        uint32_t b[3]) {
+    RO_CHECK(v && c && l && b, RO_E_ARG, "null argument");
+    uint32_t cc, ll, bb[3];
+    RO_CHECK(decode_id(v->g, id, &cc, &ll, bb), RO_E_ARG, "brick ID 0x%08x out of range", id);
+    *c = cc;
+    *l = ll;
+    b[0] = bb[0];
+    b[1] = bb[1];
+    b[2] = bb[2];
+    return RO_OK;
+}
+
+// ------------------------------------------------------------------ cache
+
+static CacheScratch cache_scratch_layout(const VolGeo &g, const ro_cache_desc &d) {
+    CacheScratch s;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    s.keys = take(sizeof(uint64_t) * d.n_slots);
+    s.hist = take(sizeof(uint32_t) * 256);
+    s.sel = take(64);
+    s.cand = take(sizeof(uint64_t) * d.max_batch);
+    s.victims = take(sizeof(uint32_t) * d.max_batch);
+    s.evicted = take(sizeof(uint32_t) * d.max_batch);
+    s.uploads = take(sizeof(uint32_t) * d.max_batch);
+    s.srcidx = take(sizeof(uint32_t) * d.max_batch);
+    s.touch = take(sizeof(uint32_t) * d.max_batch);
+    s.nblk = (uint32_t)((g.total + 1023) / 1024);
+    s.blk = take(sizeof(uint32_t) * (s.nblk + 1) * 2 + 16);
+    size_t n_slots_or_total = std::max<uint64_t>(g.total, d.n_slots);
+    s.outpairs = take(sizeof(uint32_t) * 2 * n_slots_or_total);
+    s.total = o;
+    return s;
+}
+
+static ro_status check_cache_desc(const ro_volume *v, const ro_cache_desc *d) {
+    RO_CHECK(v && d, RO_E_ARG, "null argument");
+    RO_CHECK(d->n_slots >= 1 && d->n_slots < 0x7FFFFFFFu, RO_E_ARG, "n_slots must be >= 1");
+    RO_CHECK(d->max_batch >= 1 && d->max_batch <= 8192, RO_E_ARG, "max_batch not in 1..8192");
+    return RO_OK;
+}
+
+extern "C" ro_status ro_cache_query(const ro_volume *v, const ro_cache_desc *d, ro_cache_sizes *o) {
+    ro_status st = check_cache_desc(v, d);
+    if (st) return st;
+    RO_CHECK(o, RO_E_ARG, "null output");
+    const VolGeo &g = v->g;
+    o->slot_stride = g.slot_stride;
+    o->slots = (size_t)g.slot_stride * d->n_slots;
+    o->page_table = sizeof(uint32_t) * g.total;
+    o->counters = sizeof(uint32_t) * g.total;
+    o->slot_brick = sizeof(uint32_t) * d->n_slots;
+    o->stamps = sizeof(uint32_t) * d->n_slots;
+    o->seqs = sizeof(uint32_t) * d->n_slots;
+    o->scratch = cache_scratch_layout(g, *d).total;
+    return RO_OK;
+}
+
+extern "C" ro_status ro_cache_create(const ro_volume *v, const ro_cache_desc *d,
+                                     const ro_cache_buffers *b, void *stream, ro_cache **out) {
+    ro_status st = check_cache_desc(v, d);
+    if (st) return st;
+    RO_CHECK(b && out, RO_E_ARG, "null argument");
+    RO_CHECK(b->slots && b->page_table && b->counters && b->slot_brick && b->stamps && b->seqs &&
+                 b->scratch,
+             RO_E_ARG, "null device buffer");
+    RO_CHECK(aligned(b->slots) && aligned(b->page_table) && aligned(b->counters) &&
+                 aligned(b->slot_brick) && aligned(b->stamps) && aligned(b->seqs) &&
+                 aligned(b->scratch),
+             RO_E_ARG, "device buffers must be 256-byte aligned");
+    ro_cache *c = new (std::nothrow) ro_cache;
+    RO_CHECK(c, RO_E_NOMEM, "out of host memory");
+    try {
+        c->pt_host.assign(v->g.total, kInvalid);
+        c->slot_host.assign(d->n_slots, kInvalid);
+    } catch (...) {
+        delete c;
+        RO_CHECK(false, RO_E_NOMEM, "out of host memory");
+    }
+    c->vol = const_cast<ro_volume *>(v);
+    c->desc = *d;
+    c->b = *b;
+    c->sc = cache_scratch_layout(v->g, *d);
+    c->seq_next = 0;
+    hipStream_t s = (hipStream_t)stream;
+    ro_status r;
+    if ((r = launch_fill_u32(b->page_table, v->g.total, kInvalid, s)) ||
+        (r = launch_fill_u32(b->counters, v->g.total, 0, s)) ||
+        (r = launch_fill_u32(b->slot_brick, d->n_slots, kInvalid, s)) ||
+        (r = launch_fill_u32(b->stamps, d->n_slots, 0, s)) ||
+        (r = launch_fill_u32(b->seqs, d->n_slots, 0, s))) {
+        delete c;
+        return r;
+    }
+    *out = c;
+    return RO_OK;
+}
+
+extern "C" void ro_cache_destroy(ro_cache *c) { delete c; }
+
+extern "C" ro_status ro_cache_page_table_host(const ro_cache *c, uint32_t *out, uint64_t count) {
+    RO_CHECK(c && out, RO_E_ARG, "null argument");
+    RO_CHECK(count == c->pt_host.size(), RO_E_ARG, "count must equal the brick count");
+    memcpy(out, c->pt_host.data(), sizeof(uint32_t) * count);
+    return RO_OK;
+}
+
+extern "C" ro_status ro_stream_bricks(ro_cache *c, uint32_t frame, uint32_t n,
+                                      const uint32_t *ids, const void *staged, uint8_t *flags,
+                                      void *stream) {
+    RO_CHECK(c, RO_E_ARG, "null cache");
+    RO_CHECK(n <= c->desc.max_batch, RO_E_ARG, "n = %u exceeds max_batch %u", n, c->desc.max_batch);
+    RO_CHECK(frame != kInvalid, RO_E_ARG, "frame 0xFFFFFFFF is reserved");
+    if (n == 0) return RO_OK;
+    RO_CHECK(ids && staged && flags, RO_E_ARG, "null argument");
+    RO_CHECK(aligned(staged), RO_E_ARG, "staged bricks must be 256-byte aligned");
+    const VolGeo &g = c->vol->g;
+    std::vector<uint32_t> dn(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t cc, ll, bb[3];
+        RO_CHECK(decode_id(g, ids[i], &cc, &ll, bb), RO_E_ARG, "brick ID 0x%08x out of range",
+                 ids[i]);
+        dn[i] = dense_index(g, (int)cc, (int)ll, (int)bb[0], (int)bb[1], (int)bb[2]);
+    }
+    // Host bookkeeping: flags for resident / repeated IDs, upload list.
+    std::vector<uint32_t> up, src, touch;
+    std::vector<uint8_t> f(n, 0);
+    std::vector<uint32_t> sorted_seen;
+    sorted_seen.reserve(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        auto it = std::lower_bound(sorted_seen.begin(), sorted_seen.end(), dn[i]);
+        bool dup = it != sorted_seen.end() && *it == dn[i];
+        if (!dup) sorted_seen.insert(it, dn[i]);
+        if (dup) {
+            f[i] = 2;
+        } else if (c->pt_host[dn[i]] != kInvalid) {
+            f[i] = 2;
+            touch.push_back(c->pt_host[dn[i]]);
+        } else {
+            up.push_back(dn[i]);
+            src.push_back(i);
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *sc = (uint8_t *)c->b.scratch;
+    if (!touch.empty())
+        RO_HIP(hipMemcpyAsync(sc + c->sc.touch, touch.data(), 4 * touch.size(), hipMemcpyHostToDevice, s));
+    if (!up.empty()) {
+        RO_HIP(hipMemcpyAsync(sc + c->sc.uploads, up.data(), 4 * up.size(), hipMemcpyHostToDevice, s));
+        RO_HIP(hipMemcpyAsync(sc + c->sc.srcidx, src.data(), 4 * src.size(), hipMemcpyHostToDevice, s));
+    }
+    uint32_t k_eff = 0;
+    std::vector<uint32_t> victims(up.size() + 1), evicted(up.size() + 1);
+    ro_status st = stream_bricks_device(c, frame, (uint32_t)up.size(), (uint32_t)touch.size(), staged,
+                                        s, &k_eff, victims.data(), evicted.data());
+    if (st) return st;
+    // Mirror the device's decisions.
+    for (uint32_t i = 0; i < (uint32_t)up.size(); ++i) {
+        if (i < k_eff) {
+            uint32_t slot = victims[i];
+            uint32_t old = c->slot_host[slot];
+            if (old != kInvalid) {
+                c->pt_host[old] = kInvalid;
+                c->dirty.push_back(old);
+            }
+            c->slot_host[slot] = up[i];
+            c->pt_host[up[i]] = slot;
+            c->dirty.push_back(up[i]);
+            f[src[i]] = 1;
+        } else {
+            f[src[i]] = 0;
+        }
+    }
+    c->seq_next += k_eff;
+    memcpy(flags, f.data(), n);
+    return RO_OK;
+}
+
+extern "C" ro_status ro_read_requests(ro_cache *c, uint32_t cap, uint32_t *ids, uint32_t *counts,
+                                      uint32_t *n_unique, uint64_t *total, void *stream) {
+    RO_CHECK(c && n_unique && total, RO_E_ARG, "null argument");
+    RO_CHECK(cap == 0 || (ids && counts), RO_E_ARG, "null output arrays");
+    return read_requests_device(c, cap, ids, counts, n_unique, total, (hipStream_t)stream);
+}
+
+extern "C" ro_status ro_read_usage(ro_cache *c, uint32_t frame, uint32_t cap, uint32_t *slots,
+                                   uint32_t *n_out, void *stream) {
+    RO_CHECK(c && n_out, RO_E_ARG, "null argument");
+    RO_CHECK(cap == 0 || slots, RO_E_ARG, "null output array");
+    return read_usage_device(c, frame, cap, slots, n_out, (hipStream_t)stream);
+}
+
+// ----------------------------------------------------------------- octree
+
+static ro_status tree_geometry(const ro_volume *v, const ro_octree_desc *d, TreeGeo &t) {
+    RO_CHECK(v && d, RO_E_ARG, "null argument");
+    RO_CHECK(d->depth >= 0 && d->depth <= kMaxD, RO_E_ARG, "depth %d not in 0..%d", d->depth, kMaxD);
+    memset(&t, 0, sizeof(t));
+    t.depth = d->depth;
+    int s[3];
+    for (int a = 0; a < 3; ++a) {
+        RO_CHECK(is_pow2(d->leaf[a]) && d->leaf[a] <= v->g.B, RO_E_ARG,
+                 "leaf[%d] = %d must be a power of two dividing the brick edge", a, d->leaf[a]);
+        t.leaf_log[a] = ilog2(d->leaf[a]);
+        int64_t nl = ((int64_t)v->g.dims[a] + d->leaf[a] - 1) / d->leaf[a];
+        s[a] = ilog2(nl);
+        RO_CHECK(s[a] <= d->depth, RO_E_ARG, "depth %d too small: axis %d needs %d splits", d->depth,
+                 a, s[a]);
+    }
+    uint64_t o = 0;
+    for (int l = 0; l <= d->depth; ++l) {
+        for (int a = 0; a < 3; ++a) {
+            int k = std::min(d->depth - l, s[a]);
+            t.nshift[l][a] = t.leaf_log[a] + k;
+            t.nlog[l][a] = s[a] - k;
+        }
+        t.noff[l] = (uint32_t)o;
+        o += 1ull << (t.nlog[l][0] + t.nlog[l][1] + t.nlog[l][2]);
+        RO_CHECK(o < 0xFFFFFFFFull, RO_E_CAPACITY, "too many tree nodes");
+    }
+    t.noff[d->depth + 1] = (uint32_t)o;
+    t.n_nodes = o;
+    t.n_leaves = 1ull << (t.nlog[d->depth][0] + t.nlog[d->depth][1] + t.nlog[d->depth][2]);
+    RO_CHECK(d->start_level >= 0 && d->start_level <= d->depth, RO_E_ARG,
+             "start_level %d not in 0..depth", d->start_level);
+    return RO_OK;
+}
+
+extern "C" ro_status ro_octree_query(const ro_volume *v, const ro_octree_desc *d,
+                                     ro_octree_sizes *o) {
+    TreeGeo t;
+    ro_status st = tree_geometry(v, d, t);
+    if (st) return st;
+    RO_CHECK(o, RO_E_ARG, "null output");
+    o->n_nodes = t.n_nodes;
+    o->n_leaves = t.n_leaves;
+    for (int a = 0; a < 3; ++a) o->leaf_grid[a] = 1 << t.nlog[d->depth][a];
+    o->node_meta = sizeof(uint32_t) * t.n_nodes * v->g.m;
+    o->node_mask = sizeof(uint16_t) * t.n_nodes * v->g.m;
+    o->node_flags = t.n_nodes;
+    o->scratch = 16 * 65536 + 256;  // leaf-update work items
+    return RO_OK;
+}
+
+extern "C" ro_status ro_octree_create(ro_cache *c, const ro_octree_desc *d,
+                                      const ro_octree_buffers *b, void *stream, ro_octree **out) {
+    RO_CHECK(c && b && out, RO_E_ARG, "null argument");
+    TreeGeo t;
+    ro_status st = tree_geometry(c->vol, d, t);
+    if (st) return st;
+    RO_CHECK(b->node_meta && b->node_mask && b->node_flags && b->scratch, RO_E_ARG,
+             "null device buffer");
+    RO_CHECK(aligned(b->node_meta) && aligned(b->node_mask) && aligned(b->node_flags) &&
+                 aligned(b->scratch),
+             RO_E_ARG, "device buffers must be 256-byte aligned");
+    ro_octree *o = new (std::nothrow) ro_octree;
+    RO_CHECK(o, RO_E_NOMEM, "out of host memory");
+    o->cache = c;
+    o->desc = *d;
+    o->b = *b;
+    o->t = t;
+    o->scratch_bytes = 16 * 65536 + 256;
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t nm = t.n_nodes * (uint64_t)c->vol->g.m;
+    ro_status r;
+    if ((r = launch_fill_u32(b->node_meta, nm, 0, s)) || (r = launch_fill_u16(b->node_mask, nm, 0, s)) ||
+        (r = launch_fill_u8(b->node_flags, t.n_nodes, 0, s))) {
+        delete o;
+        return r;
+    }
+    *out = o;
+    return RO_OK;
+}
+
+extern "C" void ro_octree_destroy(ro_octree *t) { delete t; }
+
+extern "C" ro_status ro_octree_set_leaf_metadata(ro_octree *t, uint32_t channel,
+                                                 const uint16_t *leaf_mm, void *stream) {
+    RO_CHECK(t && leaf_mm, RO_E_ARG, "null argument");
+    RO_CHECK(channel < (uint32_t)t->cache->vol->g.m, RO_E_ARG, "channel %u out of range", channel);
+    return octree_set_meta(t, channel, leaf_mm, (hipStream_t)stream);
+}
+
+extern "C" ro_status ro_update_residency(ro_octree *t, void *stream) {
+    RO_CHECK(t, RO_E_ARG, "null octree");
+    std::vector<uint32_t> d;
+    d.swap(t->cache->dirty);
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+    ro_status st = octree_update(t, d, (hipStream_t)stream);
+    if (st) {
+        t->cache->dirty.swap(d);  // keep the work for a retry
+        return st;
+    }
+    return RO_OK;
+}
+
+extern "C" ro_status ro_rebuild_residency(ro_octree *t, void *stream) {
+    RO_CHECK(t, RO_E_ARG, "null octree");
+    ro_status st = octree_rebuild(t, (hipStream_t)stream);
+    if (st) return st;
+    t->cache->dirty.clear();
+    return RO_OK;
+}
+
+extern "C" ro_status ro_render(ro_octree *t, const ro_frame_desc *fd, float *rgba, void *stream) {
+    RO_CHECK(t && fd && rgba, RO_E_ARG, "null argument");
+    const VolGeo &g = t->cache->vol->g;
+    RO_CHECK(aligned(rgba), RO_E_ARG, "rgba must be 256-byte aligned");
+    RO_CHECK(fd->projection == RO_PROJ_ORTHO || fd->projection == RO_PROJ_PERSP, RO_E_ARG,
+             "bad projection");
+    RO_CHECK(fd->width >= 1 && fd->height >= 1 && fd->width <= 16384 && fd->height <= 16384, RO_E_ARG,
+             "bad image size");
+    RO_CHECK(fd->step > 0.0 && fd->lod_bias > 0.0 && fd->tx > 0.0 && fd->ty > 0.0, RO_E_ARG,
+             "step, lod_bias, tx and ty must be > 0");
+    RO_CHECK(fd->n_vis >= 1 && fd->n_vis <= g.m, RO_E_ARG, "n_vis %d not in 1..%d", fd->n_vis, g.m);
+    RO_CHECK(fd->tf_dev, RO_E_ARG, "null transfer-function table");
+    RO_CHECK(fd->term_alpha > 0.0f && fd->term_alpha <= 1.0f, RO_E_ARG, "term_alpha not in (0, 1]");
+    RO_CHECK(fd->frame != kInvalid, RO_E_ARG, "frame 0xFFFFFFFF is reserved");
+    RO_CHECK(fd->start_level >= -1 && fd->start_level <= t->t.depth, RO_E_ARG, "bad start_level");
+    RO_CHECK(!(fd->flags & RO_RENDER_AOV) || fd->aov_dev, RO_E_ARG, "AOV requested without buffer");
+    uint32_t seen = 0;
+    for (int j = 0; j < fd->n_vis; ++j) {
+        RO_CHECK(fd->vis[j] >= 0 && fd->vis[j] < g.m, RO_E_ARG, "vis[%d] out of range", j);
+        RO_CHECK(!(seen >> fd->vis[j] & 1u), RO_E_ARG, "channel %d listed twice", fd->vis[j]);
+        seen |= 1u << fd->vis[j];
+        RO_CHECK(fd->lod_lo[j] >= 0 && fd->lod_lo[j] <= fd->lod_hi[j] && fd->lod_hi[j] < g.L, RO_E_ARG,
+                 "bad level range for visible slot %d", j);
+        RO_CHECK(fd->win_lo[j] < fd->win_hi[j] && fd->win_hi[j] <= (uint32_t)(65535u * 256u),
+                 RO_E_ARG, "bad window for visible slot %d", j);
+    }
+    return render_device(t, fd, rgba, (hipStream_t)stream);
+}

@@ -1,0 +1,459 @@
+// Ray-guided mixed-resolution multi-channel ray casting over the residency
+// octree (Sec. 6.1, Alg. 1; Sec. 6.2; Sec. 6 implementation notes).
+//
+// One lane per pixel.  Sample positions and every integer decision derived
+// from them (box, leaf, brick, level) are computed in FP64; interpolation,
+// transfer functions and the channel mix in FP32; the compositing state in
+// FP64.  Per lane, the state of the current (leaf, level) visit is cached:
+// which channels are empty there, the slot each channel samples, and which
+// channels miss their desired brick; misses are counted once per visit with
+// the visit's sample count (one atomic per visit and channel).
+#include <math.h>
+#include <string.h>
+
+#include "common.h"
+
+namespace ro {
+
+struct RenderArgs {
+    VolGeo g;
+    TreeGeo t;
+    double eye[3], F[3], R[3], U[3];
+    double tx, ty;
+    double step;
+    int32_t proj, W, H;
+    int32_t start_level;
+    uint32_t K[kMaxL];  // level l is desired from sample index K[l] on (l >= 1)
+    int32_t nvis;
+    int32_t vis[kMaxC];
+    int32_t lo[kMaxC], hi[kMaxC];
+    uint32_t W0[kMaxC], W1[kMaxC];
+    float w0[kMaxC], iw[kMaxC];
+    float term;
+    uint32_t frame;
+    uint32_t flags;
+    const uint8_t *slots;
+    const uint32_t *pt;
+    uint32_t *cnt;
+    uint32_t *stamp;
+    const uint32_t *meta;
+    const uint16_t *mask;
+    const float4 *tf;
+    float *rgba;
+    uint32_t *aov;
+};
+
+// Zero-alpha runs of a channel's table as raw-value bounds: the range
+// [mn, mx] is empty iff some run has mn >= lo and mx <= hi.  Raw values are
+// at most 65535, so runs whose lower bound exceeds that are dropped and
+// upper bounds are clamped to 65535.
+struct RunTable {
+    uint16_t lo[kMaxRuns], hi[kMaxRuns];
+};
+
+__device__ inline bool range_empty(uint32_t mm, const RunTable &rt, int nr) {
+    uint32_t mn = mm & 0xFFFFu, mx = mm >> 16;
+    for (int r = 0; r < nr; ++r)
+        if (mn >= rt.lo[r] && mx <= rt.hi[r]) return true;
+    return false;
+}
+
+// Build the run table of one channel (one thread): entries a..b maximal with
+// alpha == 0.  Raw bounds from the window (24.8 fixed point, den = W1 - W0):
+// floor(255 (256 r - W0) / den) >= a  <=>  r >= ceil((255 W0 + a den) / 65280)
+// ceil (255 (256 r - W0) / den) <= b  <=>  r <= floor((255 W0 + b den) / 65280)
+__device__ inline int build_runs(const float4 *tf, uint32_t W0, uint32_t W1, RunTable &rt) {
+    int n = 0;
+    int e = 0;
+    const uint64_t den = (uint64_t)W1 - (uint64_t)W0;
+    while (e < 256) {
+        if (tf[e].w != 0.0f) {
+            ++e;
+            continue;
+        }
+        int a = e;
+        while (e < 256 && tf[e].w == 0.0f) ++e;
+        int b = e - 1;
+        uint64_t rlo = a == 0 ? 0 : (255ull * W0 + (uint64_t)a * den + 65279ull) / 65280ull;
+        uint64_t rhi = b == 255 ? 65535ull : (255ull * W0 + (uint64_t)b * den) / 65280ull;
+        if (rhi > 65535ull) rhi = 65535ull;
+        if (rlo <= rhi && n < kMaxRuns) {
+            rt.lo[n] = (uint16_t)rlo;
+            rt.hi[n] = (uint16_t)rhi;
+            ++n;
+        }
+    }
+    return n;
+}
+
+template <int BPV>
+__device__ inline float voxel(const uint8_t *p, uint32_t idx) {
+    if (BPV == 1) return (float)p[idx];
+    return (float)((const uint16_t *)p)[idx];
+}
+
+template <int NV, int BPV, bool AOV>
+__global__ void __launch_bounds__(256) k_render(const RenderArgs A) {
+    extern __shared__ float4 s_tf[];  // [nvis][256]
+    __shared__ RunTable s_runs[NV];
+    __shared__ int s_nruns[NV];
+    __shared__ uint32_t s_lsh[kMaxL];  // packed per-level axis shifts
+
+    const int nvis = A.nvis;
+    for (int i = threadIdx.x; i < nvis * 256; i += blockDim.x) s_tf[i] = A.tf[i];
+    if (threadIdx.x < (unsigned)A.g.L)
+        s_lsh[threadIdx.x] = (uint32_t)A.g.lshift[threadIdx.x][0] | ((uint32_t)A.g.lshift[threadIdx.x][1] << 8) |
+                             ((uint32_t)A.g.lshift[threadIdx.x][2] << 16);
+    __syncthreads();
+    if (threadIdx.x < (unsigned)nvis)
+        s_nruns[threadIdx.x] = build_runs(s_tf + threadIdx.x * 256, A.W0[threadIdx.x], A.W1[threadIdx.x],
+                                          s_runs[threadIdx.x]);
+    __syncthreads();
+
+    const int px = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int py = blockIdx.y * 16 + (threadIdx.x >> 4);
+    if (px >= A.W || py >= A.H) return;
+    const VolGeo &g = A.g;
+    const TreeGeo &T = A.t;
+    const int D = T.depth;
+
+    // ---- ray in L0 voxel units
+    double o[3], d[3];
+    {
+        double a = (double)(2 * px + 1 - A.W) / (double)A.W;
+        double b = (double)(A.H - 2 * py - 1) / (double)A.H;
+        double ow[3], dw[3];
+        if (A.proj == RO_PROJ_ORTHO) {
+            for (int k = 0; k < 3; ++k) {
+                ow[k] = A.eye[k] + a * A.tx * A.R[k] + b * A.ty * A.U[k];
+                dw[k] = A.F[k];
+            }
+        } else {
+            double n = 0;
+            for (int k = 0; k < 3; ++k) {
+                ow[k] = A.eye[k];
+                dw[k] = A.F[k] + a * A.tx * A.R[k] + b * A.ty * A.U[k];
+                n += dw[k] * dw[k];
+            }
+            n = sqrt(n);
+            for (int k = 0; k < 3; ++k) dw[k] = dw[k] / n;
+        }
+        for (int k = 0; k < 3; ++k) {
+            o[k] = ow[k] / g.spacing[k];
+            d[k] = dw[k] / g.spacing[k];
+        }
+    }
+    double Cr = 0, Cg = 0, Cb = 0, Tr = 1.0;
+    const double one_minus_term = 1.0 - (double)A.term;
+    float *out = A.rgba + ((size_t)py * A.W + px) * 4;
+
+    // ---- box interval
+    double t0 = -INFINITY, t1 = INFINITY;
+    bool hit = true;
+    for (int k = 0; k < 3; ++k) {
+        if (d[k] == 0.0) {
+            if (o[k] < 0.0 || o[k] >= (double)g.dims[k]) hit = false;
+            continue;
+        }
+        double u = (0.0 - o[k]) / d[k], v = ((double)g.dims[k] - o[k]) / d[k];
+        if (u > v) {
+            double s = u;
+            u = v;
+            v = s;
+        }
+        t0 = fmax(t0, u);
+        t1 = fmin(t1, v);
+    }
+    if (!hit || t0 > t1) {
+        out[0] = out[1] = out[2] = out[3] = 0.0f;
+        return;
+    }
+    long long k = (long long)floor(t0 / A.step) - 1;
+    if (k < 0) k = 0;
+    const long long kend = (long long)ceil(t1 / A.step) + 1;
+
+    // ---- visit state
+    uint32_t cur_leaf = kInvalid;
+    int cur_lod = -1, lod = 0;
+    while (lod + 1 < g.L && (uint64_t)k >= A.K[lod + 1]) ++lod;
+    uint32_t emask = 0, missmask = 0;
+    uint32_t slot[NV];
+    uint64_t lvpack = 0;
+    uint32_t nvisit = 0;
+    int lc[3] = {0, 0, 0};  // leaf coordinates of the visit
+#pragma unroll
+    for (int j = 0; j < NV; ++j) slot[j] = kInvalid;
+    const int s0 = A.start_level;
+
+    auto flush = [&]() {
+        if (missmask && nvisit) {
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                if (j < nvis && ((missmask >> j) & 1u)) {
+                    int ls = min(max(cur_lod, A.lo[j]), A.hi[j]);
+                    uint32_t sh = s_lsh[ls];
+                    int bx = (lc[0] << T.leaf_log[0]) >> (g.Blog + (int)(sh & 255u));
+                    int by = (lc[1] << T.leaf_log[1]) >> (g.Blog + (int)((sh >> 8) & 255u));
+                    int bz = (lc[2] << T.leaf_log[2]) >> (g.Blog + (int)((sh >> 16) & 255u));
+                    atomicAdd(&A.cnt[dense_index(g, A.vis[j], ls, bx, by, bz)], nvisit);
+                }
+            }
+        }
+        nvisit = 0;
+    };
+
+    for (; k <= kend; ) {
+        const double t = (double)k * A.step;
+        double u[3];
+        bool inside = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            u[a] = o[a] + t * d[a];
+            inside = inside && (u[a] >= 0.0) && (u[a] < (double)g.dims[a]);
+        }
+        if (!inside) {
+            ++k;
+            continue;
+        }
+        const int iu[3] = {(int)u[0], (int)u[1], (int)u[2]};
+        while (lod + 1 < g.L && (uint64_t)k >= A.K[lod + 1]) ++lod;
+        const int nl[3] = {iu[0] >> T.leaf_log[0], iu[1] >> T.leaf_log[1], iu[2] >> T.leaf_log[2]};
+        const uint32_t leaf = node_index(T, D, nl[0], nl[1], nl[2]);
+        if (leaf != cur_leaf || lod != cur_lod) {
+            flush();
+            if (leaf != cur_leaf) {
+                // descend from the start level; skip the first node that is
+                // empty for every visible channel (the leaf included)
+                const bool noskip = (A.flags & RO_RENDER_NO_SKIP) != 0;
+                bool skipped = false;
+                for (int dl = noskip ? D : s0; dl <= D; ++dl) {
+                    const uint32_t nd = node_index(T, dl, iu[0] >> T.nshift[dl][0], iu[1] >> T.nshift[dl][1],
+                                                   iu[2] >> T.nshift[dl][2]);
+                    uint32_t em = 0;
+                    for (int j = 0; j < nvis; ++j)
+                        if (range_empty(A.meta[(size_t)nd * g.m + A.vis[j]], s_runs[j], s_nruns[j])) em |= 1u << j;
+                    const bool all = em == (1u << nvis) - 1u;
+                    if (dl == D) emask = em;
+                    if (all && !noskip) {
+                        double te = INFINITY;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            if (d[a] == 0.0) continue;
+                            const int sh = T.nshift[dl][a];
+                            const double lo_a = (double)((iu[a] >> sh) << sh);
+                            const double bound = d[a] > 0.0 ? lo_a + (double)(1 << sh) : lo_a;
+                            te = fmin(te, (bound - o[a]) / d[a]);
+                        }
+                        long long kn = (long long)floor(te / A.step) - 1;
+                        k = kn > k + 1 ? kn : k + 1;
+                        skipped = true;
+                        break;
+                    }
+                    if (!all && dl < D) {
+                        // not empty for every channel here: go one level down
+                        continue;
+                    }
+                }
+                if (skipped) {
+                    cur_leaf = kInvalid;
+                    continue;
+                }
+                cur_leaf = leaf;
+                lc[0] = nl[0];
+                lc[1] = nl[1];
+                lc[2] = nl[2];
+                // every channel empty here (only without skipping): the
+                // sample contributes nothing
+            }
+            cur_lod = lod;
+            missmask = 0;
+            lvpack = 0;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                uint32_t ns = kInvalid;
+                if (j < nvis && !((emask >> j) & 1u)) {
+                    const int c = A.vis[j];
+                    const int ls = min(max(lod, A.lo[j]), A.hi[j]);
+                    const uint32_t mk = (uint32_t)A.mask[(size_t)leaf * g.m + c] >> ls;
+                    if (!(mk & 1u)) missmask |= 1u << j;
+                    if (mk) {
+                        const int lu = ls + __builtin_ctz(mk);
+                        const uint32_t sh = s_lsh[lu];
+                        const int bx = iu[0] >> (g.Blog + (int)(sh & 255u));
+                        const int by = iu[1] >> (g.Blog + (int)((sh >> 8) & 255u));
+                        const int bz = iu[2] >> (g.Blog + (int)((sh >> 16) & 255u));
+                        ns = A.pt[dense_index(g, c, lu, bx, by, bz)];
+                        if (ns != kInvalid) {
+                            lvpack |= (uint64_t)lu << (4 * j);
+                            if (ns != slot[j]) A.stamp[ns] = A.frame;
+                        }
+                    }
+                }
+                slot[j] = ns;
+            }
+        }
+        ++nvisit;
+        // ---- sample every visible channel
+        float prod = 1.0f, sa = 0.0f, sr = 0.0f, sg = 0.0f, sbl = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            if (j < nvis && slot[j] != kInvalid) {
+                const int lu = (int)((lvpack >> (4 * j)) & 15u);
+                const uint32_t sh = s_lsh[lu];
+                int i0[3];
+                float fr[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int s = (int)((sh >> (8 * a)) & 255u);
+                    const double ul = ldexp(u[a], -s);
+                    const int b = (iu[a] >> (g.Blog + s)) << g.Blog;
+                    const double q = ul + 0.5 - (double)b;
+                    i0[a] = (int)q;
+                    fr[a] = (float)(q - (double)i0[a]);
+                }
+                const uint8_t *base = A.slots + (size_t)slot[j] * g.slot_stride;
+                const uint32_t E = (uint32_t)g.E;
+                const uint32_t idx = ((uint32_t)i0[2] * E + (uint32_t)i0[1]) * E + (uint32_t)i0[0];
+                const float v000 = voxel<BPV>(base, idx), v100 = voxel<BPV>(base, idx + 1);
+                const float v010 = voxel<BPV>(base, idx + E), v110 = voxel<BPV>(base, idx + E + 1);
+                const float v001 = voxel<BPV>(base, idx + E * E), v101 = voxel<BPV>(base, idx + E * E + 1);
+                const float v011 = voxel<BPV>(base, idx + E * E + E), v111 = voxel<BPV>(base, idx + E * E + E + 1);
+                const float c00 = v000 + (v100 - v000) * fr[0];
+                const float c10 = v010 + (v110 - v010) * fr[0];
+                const float c01 = v001 + (v101 - v001) * fr[0];
+                const float c11 = v011 + (v111 - v011) * fr[0];
+                const float e0 = c00 + (c10 - c00) * fr[1];
+                const float e1 = c01 + (c11 - c01) * fr[1];
+                const float v = e0 + (e1 - e0) * fr[2];
+                float x = (v - A.w0[j]) * A.iw[j];
+                x = fminf(fmaxf(x, 0.0f), 1.0f);
+                const float p = x * 255.0f;
+                int e = (int)p;
+                e = e > 255 ? 255 : e;
+                const int e1i = e < 255 ? e + 1 : 255;
+                const float f = p - (float)e;
+                const float4 ta = s_tf[j * 256 + e], tb = s_tf[j * 256 + e1i];
+                const float al = ta.w + (tb.w - ta.w) * f;
+                const float r = ta.x + (tb.x - ta.x) * f;
+                const float gg = ta.y + (tb.y - ta.y) * f;
+                const float bb = ta.z + (tb.z - ta.z) * f;
+                prod *= 1.0f - al;
+                sa += al;
+                sr += al * r;
+                sg += al * gg;
+                sbl += al * bb;
+                if (AOV) A.aov[((size_t)py * A.W + px) * g.L + lu] += 1;
+            }
+        }
+        if (sa > 0.0f) {
+            const float as = 1.0f - prod;
+            const float sc = as / sa;
+            Cr += Tr * (double)(sr * sc);
+            Cg += Tr * (double)(sg * sc);
+            Cb += Tr * (double)(sbl * sc);
+            Tr *= 1.0 - (double)as;
+            if (Tr <= one_minus_term) break;
+        }
+        ++k;
+    }
+    flush();
+    out[0] = (float)Cr;
+    out[1] = (float)Cg;
+    out[2] = (float)Cb;
+    out[3] = (float)(1.0 - Tr);
+}
+
+template <int NV, int BPV, bool AOV>
+static hipError_t launch_one(const RenderArgs &A, dim3 grid, size_t lds, hipStream_t s) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_render<NV, BPV, AOV>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_render<NV, BPV, AOV>), grid, dim3(256), lds, s, A);
+    return hipGetLastError();
+}
+
+template <int NV, int BPV>
+static hipError_t launch_nv(const RenderArgs &A, bool aov, dim3 grid, size_t lds, hipStream_t s) {
+    return aov ? launch_one<NV, BPV, true>(A, grid, lds, s) : launch_one<NV, BPV, false>(A, grid, lds, s);
+}
+
+template <int BPV>
+static hipError_t launch_bpv(const RenderArgs &A, bool aov, dim3 grid, size_t lds, hipStream_t s) {
+    if (A.nvis <= 1) return launch_nv<1, BPV>(A, aov, grid, lds, s);
+    if (A.nvis <= 2) return launch_nv<2, BPV>(A, aov, grid, lds, s);
+    if (A.nvis <= 4) return launch_nv<4, BPV>(A, aov, grid, lds, s);
+    if (A.nvis <= 8) return launch_nv<8, BPV>(A, aov, grid, lds, s);
+    return launch_nv<16, BPV>(A, aov, grid, lds, s);
+}
+
+ro_status render_device(ro_octree *tr, const ro_frame_desc *fd, float *rgba, hipStream_t s) {
+    const ro_cache *c = tr->cache;
+    RenderArgs A;
+    memset(&A, 0, sizeof(A));
+    A.g = c->vol->g;
+    A.t = tr->t;
+    for (int k = 0; k < 3; ++k) {
+        A.eye[k] = fd->eye[k];
+        A.F[k] = fd->forward[k];
+        A.R[k] = fd->right[k];
+        A.U[k] = fd->up[k];
+    }
+    A.tx = fd->tx;
+    A.ty = fd->ty;
+    A.step = fd->step;
+    A.proj = fd->projection;
+    A.W = fd->width;
+    A.H = fd->height;
+    A.start_level = fd->start_level >= 0 ? fd->start_level : tr->desc.start_level;
+    // desired level thresholds: level l from the first sample k with
+    // k * step >= D_l, D_l = s_l / (lod_bias * 2 ty / H)
+    const double pix = 2.0 * fd->ty / fd->height;
+    for (int l = 0; l < kMaxL; ++l) A.K[l] = kInvalid;
+    A.K[0] = 0;
+    for (int l = 1; l < A.g.L; ++l) {
+        const double s_l = (double)(1 << A.g.lshift[l][0]) * A.g.spacing[0];
+        if (fd->projection == RO_PROJ_ORTHO) {
+            A.K[l] = fd->lod_bias * pix >= s_l ? 0u : kInvalid;
+        } else {
+            const double Dl = s_l / (fd->lod_bias * pix);
+            double q = ceil(Dl / fd->step);
+            if (!(q < 4.0e9)) {
+                A.K[l] = kInvalid;
+                continue;
+            }
+            long long kk = (long long)q;
+            while (kk > 0 && (double)(kk - 1) * fd->step >= Dl) --kk;
+            while ((double)kk * fd->step < Dl) ++kk;
+            A.K[l] = kk < 0xFFFFFFFFll ? (uint32_t)kk : kInvalid;
+        }
+    }
+    A.nvis = fd->n_vis;
+    for (int j = 0; j < fd->n_vis; ++j) {
+        A.vis[j] = fd->vis[j];
+        A.lo[j] = fd->lod_lo[j];
+        A.hi[j] = fd->lod_hi[j];
+        A.W0[j] = fd->win_lo[j];
+        A.W1[j] = fd->win_hi[j];
+        A.w0[j] = (float)(fd->win_lo[j] / 256.0);
+        A.iw[j] = (float)(256.0 / ((double)fd->win_hi[j] - (double)fd->win_lo[j]));
+    }
+    A.term = fd->term_alpha;
+    A.frame = fd->frame;
+    A.flags = fd->flags;
+    A.slots = (const uint8_t *)c->b.slots;
+    A.pt = c->b.page_table;
+    A.cnt = c->b.counters;
+    A.stamp = c->b.stamps;
+    A.meta = tr->b.node_meta;
+    A.mask = tr->b.node_mask;
+    A.tf = (const float4 *)fd->tf_dev;
+    A.rgba = rgba;
+    A.aov = fd->aov_dev;
+    dim3 grid((fd->width + 15) / 16, (fd->height + 15) / 16);
+    size_t lds = sizeof(float4) * 256 * (size_t)fd->n_vis;
+    const bool aov = (fd->flags & RO_RENDER_AOV) != 0;
+    RO_HIP(A.g.bpv == 1 ? launch_bpv<1>(A, aov, grid, lds, s) : launch_bpv<2>(A, aov, grid, lds, s));
+    return RO_OK;
+}
+
+}  // namespace ro

@@ -1,0 +1,94 @@
+"""Host-side frame loop over the C ABI: scene set-up from a volume source,
+brick staging, rendering and plain request-driven streaming.
+
+A volume source is anything with the generator's interface: dims, spacing,
+n_channels, bits, n_levels, bricks(c, l, coords, B) -> [n][E][E][E] and
+leaf_minmax(c, leaf, leaf_grid) -> [n_leaves][2] (the data server's bricks
+and metadata answers).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import resoct
+
+
+class GpuScene:
+    def __init__(self, src, brick: int, leaf, depth: int, n_slots: int, max_batch: int = 4096,
+                 start_level: int = 0, device="cuda", set_metadata=True):
+        self.src = src
+        self.device = device
+        self.vol = resoct.Volume(src.dims, src.spacing, src.n_channels, 1 if src.bits == 8 else 2,
+                                 brick, src.n_levels)
+        self.cache = resoct.Cache(self.vol, n_slots, max_batch, device=device)
+        self.tree = resoct.Octree(self.cache, leaf, depth, start_level, device=device)
+        self.B = brick
+        self.E = brick + 2
+        self.leaf = tuple(leaf)
+        self.ldims, self.lf, self.nb = self.vol.levels()
+        self.np_dtype = np.uint8 if src.bits == 8 else np.uint16
+        if set_metadata:
+            for c in range(src.n_channels):
+                self.set_metadata(c, src.leaf_minmax(c, self.leaf, self.tree.leaf_grid))
+
+    def set_metadata(self, c, leaf_mm: np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(leaf_mm, dtype=np.uint16).reshape(-1).view(np.int16))
+        t = t.to(self.device).view(torch.uint16)
+        self.tree.set_leaf_metadata(c, t)
+        torch.cuda.current_stream().synchronize()
+
+    # ------------------------------------------------------------- bricks
+    def all_ids(self, channels=None, levels=None):
+        ids = []
+        for c in (range(self.vol.n_channels) if channels is None else channels):
+            for l in (range(self.vol.n_levels) if levels is None else levels):
+                nx, ny, nz = self.nb[l]
+                for bz in range(nz):
+                    for by in range(ny):
+                        for bx in range(nx):
+                            ids.append(self.vol.encode(c, l, (bx, by, bz)))
+        return np.array(ids, dtype=np.uint32)
+
+    def stage(self, ids) -> torch.Tensor:
+        """Fetch the bricks of `ids` from the source and pack them at the
+        cache's slot stride in device memory."""
+        n = len(ids)
+        stride = self.cache.slot_stride
+        host = np.zeros((max(n, 1), stride), np.uint8)
+        groups = {}
+        for i, id_ in enumerate(ids):
+            c, l, b = self.vol.decode(int(id_))
+            groups.setdefault((c, l), []).append((i, b))
+        nbytes = self.E ** 3 * (1 if self.np_dtype == np.uint8 else 2)
+        for (c, l), lst in groups.items():
+            br = self.src.bricks(c, l, [b for _, b in lst], self.B)
+            raw = np.ascontiguousarray(br).view(np.uint8).reshape(len(lst), nbytes)
+            for k, (i, _) in enumerate(lst):
+                host[i, :nbytes] = raw[k]
+        return torch.from_numpy(host.reshape(-1)).to(self.device)
+
+    def upload(self, frame: int, ids, staged: torch.Tensor = None) -> np.ndarray:
+        ids = np.asarray(ids, dtype=np.uint32)
+        flags = np.zeros(0, np.uint8)
+        for s in range(0, len(ids), self.cache.max_batch):
+            part = ids[s:s + self.cache.max_batch]
+            st = self.stage(part) if staged is None else staged[s * self.cache.slot_stride:]
+            flags = np.concatenate([flags, self.cache.stream_bricks(frame, part, st)])
+        return flags
+
+    # ------------------------------------------------------------- frames
+    def tf_tensor(self, channels) -> torch.Tensor:
+        return torch.from_numpy(np.stack([np.asarray(ch["tf"], np.float32) for ch in channels])) \
+            .contiguous().to(self.device)
+
+    def render(self, frame, cam, W, H, step, channels, tf_dev=None, out=None, aov=False, **kw):
+        tf_dev = self.tf_tensor(channels) if tf_dev is None else tf_dev
+        out = torch.empty(H * W * 4, dtype=torch.float32, device=self.device) if out is None else out
+        aov_t = torch.zeros(H * W * self.vol.n_levels, dtype=torch.int32, device=self.device) if aov else None
+        fd = resoct.frame_desc(frame, cam, W, H, step, channels, tf_dev, self.vol.n_levels, aov=aov_t, **kw)
+        self.tree.render(fd, out)
+        res = {"rgba": out, "fd": fd, "tf": tf_dev}
+        if aov:
+            res["aov"] = aov_t
+        return res

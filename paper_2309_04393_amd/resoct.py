@@ -1,0 +1,335 @@
+"""Thin ctypes binding of libresoct.so (the C ABI in include/resoct.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch provides device memory (each buffer the *_query calls
+size) and streams.  Importing this module fails loudly when the built
+library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libresoct.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                      "python paper_2309_04393_amd/build.py")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MAX_CHANNELS = 16
+MAX_LEVELS = 16
+INVALID = 0xFFFFFFFF
+PROJ_ORTHO, PROJ_PERSP = 0, 1
+RENDER_NO_SKIP, RENDER_AOV = 1, 2
+
+c_i32, c_u32, c_u64, c_sz, c_vp, c_dbl = (ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
+                                          ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double)
+
+
+class VolumeDesc(ctypes.Structure):
+    _fields_ = [("dims", c_i32 * 3), ("spacing", c_dbl * 3), ("n_channels", c_i32),
+                ("bytes_per_voxel", c_i32), ("brick", c_i32), ("n_levels", c_i32)]
+
+
+class CacheDesc(ctypes.Structure):
+    _fields_ = [("n_slots", c_u32), ("max_batch", c_u32)]
+
+
+class CacheSizes(ctypes.Structure):
+    _fields_ = [("slots", c_sz), ("page_table", c_sz), ("counters", c_sz), ("slot_brick", c_sz),
+                ("stamps", c_sz), ("seqs", c_sz), ("scratch", c_sz), ("slot_stride", c_sz)]
+
+
+class CacheBuffers(ctypes.Structure):
+    _fields_ = [("slots", c_vp), ("page_table", c_vp), ("counters", c_vp), ("slot_brick", c_vp),
+                ("stamps", c_vp), ("seqs", c_vp), ("scratch", c_vp)]
+
+
+class OctreeDesc(ctypes.Structure):
+    _fields_ = [("leaf", c_i32 * 3), ("depth", c_i32), ("start_level", c_i32)]
+
+
+class OctreeSizes(ctypes.Structure):
+    _fields_ = [("node_meta", c_sz), ("node_mask", c_sz), ("node_flags", c_sz), ("scratch", c_sz),
+                ("n_nodes", c_u64), ("n_leaves", c_u64), ("leaf_grid", c_i32 * 3)]
+
+
+class OctreeBuffers(ctypes.Structure):
+    _fields_ = [("node_meta", c_vp), ("node_mask", c_vp), ("node_flags", c_vp), ("scratch", c_vp)]
+
+
+class FrameDesc(ctypes.Structure):
+    _fields_ = [("frame", c_u32), ("projection", c_i32), ("eye", c_dbl * 3), ("forward", c_dbl * 3),
+                ("right", c_dbl * 3), ("up", c_dbl * 3), ("tx", c_dbl), ("ty", c_dbl),
+                ("width", c_i32), ("height", c_i32), ("step", c_dbl), ("lod_bias", c_dbl),
+                ("n_vis", c_i32), ("vis", c_i32 * MAX_CHANNELS), ("lod_lo", c_i32 * MAX_CHANNELS),
+                ("lod_hi", c_i32 * MAX_CHANNELS), ("win_lo", c_u32 * MAX_CHANNELS),
+                ("win_hi", c_u32 * MAX_CHANNELS), ("tf_dev", c_vp), ("term_alpha", ctypes.c_float),
+                ("start_level", c_i32), ("flags", c_u32), ("aov_dev", c_vp)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_P = ctypes.POINTER
+_sig("ro_last_error", ctypes.c_char_p, [])
+_sig("ro_volume_create", c_i32, [_P(VolumeDesc), _P(c_vp)])
+_sig("ro_volume_destroy", None, [c_vp])
+_sig("ro_volume_levels", c_i32, [c_vp, c_vp, c_vp, c_vp])
+_sig("ro_volume_brick_count", c_i32, [c_vp, _P(c_u64)])
+_sig("ro_brick_id_encode", c_i32, [c_vp, c_u32, c_u32, _P(c_u32 * 3), _P(c_u32)])
+_sig("ro_brick_id_decode", c_i32, [c_vp, c_u32, _P(c_u32), _P(c_u32), _P(c_u32 * 3)])
+_sig("ro_cache_query", c_i32, [c_vp, _P(CacheDesc), _P(CacheSizes)])
+_sig("ro_cache_create", c_i32, [c_vp, _P(CacheDesc), _P(CacheBuffers), c_vp, _P(c_vp)])
+_sig("ro_cache_destroy", None, [c_vp])
+_sig("ro_stream_bricks", c_i32, [c_vp, c_u32, c_u32, c_vp, c_vp, c_vp, c_vp])
+_sig("ro_read_requests", c_i32, [c_vp, c_u32, c_vp, c_vp, _P(c_u32), _P(c_u64), c_vp])
+_sig("ro_read_usage", c_i32, [c_vp, c_u32, c_u32, c_vp, _P(c_u32), c_vp])
+_sig("ro_cache_page_table_host", c_i32, [c_vp, c_vp, c_u64])
+_sig("ro_octree_query", c_i32, [c_vp, _P(OctreeDesc), _P(OctreeSizes)])
+_sig("ro_octree_create", c_i32, [c_vp, _P(OctreeDesc), _P(OctreeBuffers), c_vp, _P(c_vp)])
+_sig("ro_octree_destroy", None, [c_vp])
+_sig("ro_octree_set_leaf_metadata", c_i32, [c_vp, c_u32, c_vp, c_vp])
+_sig("ro_update_residency", c_i32, [c_vp, c_vp])
+_sig("ro_rebuild_residency", c_i32, [c_vp, c_vp])
+_sig("ro_render", c_i32, [c_vp, _P(FrameDesc), c_vp, c_vp])
+
+
+class ResoctError(RuntimeError):
+    def __init__(self, code, where):
+        msg = _lib.ro_last_error().decode(errors="replace")
+        super().__init__(f"{where} failed ({code}): {msg}")
+        self.code = code
+
+
+def _check(code, where):
+    if code != 0:
+        raise ResoctError(code, where)
+
+
+def last_error() -> str:
+    return _lib.ro_last_error().decode(errors="replace")
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_vp(stream.cuda_stream)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(c_vp)
+
+
+def _dev_ptr(t: torch.Tensor):
+    return c_vp(t.data_ptr())
+
+
+def _alloc(nbytes: int, device) -> torch.Tensor:
+    # 256-byte aligned: the caching allocator returns 512-byte aligned blocks
+    t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+class Volume:
+    def __init__(self, dims, spacing, n_channels, bytes_per_voxel, brick, n_levels):
+        d = VolumeDesc()
+        d.dims[:] = [int(x) for x in dims]
+        d.spacing[:] = [float(x) for x in spacing]
+        d.n_channels, d.bytes_per_voxel, d.brick, d.n_levels = n_channels, bytes_per_voxel, brick, n_levels
+        h = c_vp()
+        _check(_lib.ro_volume_create(ctypes.byref(d), ctypes.byref(h)), "ro_volume_create")
+        self.h = h
+        self.desc = d
+        self.n_channels, self.n_levels, self.brick = n_channels, n_levels, brick
+        self.bytes_per_voxel = bytes_per_voxel
+        self.dims = tuple(int(x) for x in dims)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.ro_volume_destroy(self.h)
+            self.h = None
+
+    def levels(self):
+        L = self.n_levels
+        d = np.zeros((L, 3), np.int32)
+        f = np.zeros((L, 3), np.int32)
+        nb = np.zeros((L, 3), np.int32)
+        _check(_lib.ro_volume_levels(self.h, _np_ptr(d), _np_ptr(f), _np_ptr(nb)), "ro_volume_levels")
+        return d, f, nb
+
+    def brick_count(self) -> int:
+        n = c_u64()
+        _check(_lib.ro_volume_brick_count(self.h, ctypes.byref(n)), "ro_volume_brick_count")
+        return int(n.value)
+
+    def encode(self, c, l, b) -> int:
+        arr = (c_u32 * 3)(*[int(x) for x in b])
+        out = c_u32()
+        _check(_lib.ro_brick_id_encode(self.h, c, l, ctypes.byref(arr), ctypes.byref(out)),
+               "ro_brick_id_encode")
+        return int(out.value)
+
+    def decode(self, id_):
+        c, l, b = c_u32(), c_u32(), (c_u32 * 3)()
+        _check(_lib.ro_brick_id_decode(self.h, id_, ctypes.byref(c), ctypes.byref(l), ctypes.byref(b)),
+               "ro_brick_id_decode")
+        return int(c.value), int(l.value), tuple(int(x) for x in b)
+
+
+class Cache:
+    def __init__(self, vol: Volume, n_slots: int, max_batch: int, device="cuda", stream=None):
+        self.vol = vol
+        d = CacheDesc(n_slots, max_batch)
+        sz = CacheSizes()
+        _check(_lib.ro_cache_query(vol.h, ctypes.byref(d), ctypes.byref(sz)), "ro_cache_query")
+        self.sizes = sz
+        self.slot_stride = int(sz.slot_stride)
+        self.n_slots, self.max_batch = n_slots, max_batch
+        self.t = {name: _alloc(getattr(sz, name), device) for name in
+                  ("slots", "page_table", "counters", "slot_brick", "stamps", "seqs", "scratch")}
+        b = CacheBuffers(*[self.t[n].data_ptr() for n in
+                           ("slots", "page_table", "counters", "slot_brick", "stamps", "seqs", "scratch")])
+        h = c_vp()
+        _check(_lib.ro_cache_create(vol.h, ctypes.byref(d), ctypes.byref(b), _stream(stream),
+                                    ctypes.byref(h)), "ro_cache_create")
+        self.h = h
+        self.n_bricks = vol.brick_count()
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.ro_cache_destroy(self.h)
+            self.h = None
+
+    def staging(self, n: int, device="cuda") -> torch.Tensor:
+        return torch.zeros(max(n, 1) * self.slot_stride, dtype=torch.uint8, device=device)
+
+    def stream_bricks(self, frame: int, ids, staged: torch.Tensor, stream=None) -> np.ndarray:
+        ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
+        n = len(ids)
+        flags = np.zeros(max(n, 1), np.uint8)
+        if n:
+            assert staged.numel() >= n * self.slot_stride
+        _check(_lib.ro_stream_bricks(self.h, frame, n, _np_ptr(ids), _dev_ptr(staged) if n else None,
+                                     _np_ptr(flags), _stream(stream)), "ro_stream_bricks")
+        return flags[:n]
+
+    def read_requests(self, cap: int, stream=None):
+        ids = np.zeros(max(cap, 1), np.uint32)
+        cnt = np.zeros(max(cap, 1), np.uint32)
+        nu, tot = c_u32(), c_u64()
+        _check(_lib.ro_read_requests(self.h, cap, _np_ptr(ids), _np_ptr(cnt), ctypes.byref(nu),
+                                     ctypes.byref(tot), _stream(stream)), "ro_read_requests")
+        k = min(cap, nu.value)
+        return ids[:k], cnt[:k], int(nu.value), int(tot.value)
+
+    def read_usage(self, frame: int, cap: int = None, stream=None):
+        cap = self.n_slots if cap is None else cap
+        out = np.zeros(max(cap, 1), np.uint32)
+        n = c_u32()
+        _check(_lib.ro_read_usage(self.h, frame, cap, _np_ptr(out), ctypes.byref(n), _stream(stream)),
+               "ro_read_usage")
+        return out[:min(cap, n.value)], int(n.value)
+
+    def page_table_host(self) -> np.ndarray:
+        out = np.zeros(self.n_bricks, np.uint32)
+        _check(_lib.ro_cache_page_table_host(self.h, _np_ptr(out), self.n_bricks),
+               "ro_cache_page_table_host")
+        return out
+
+
+class Octree:
+    def __init__(self, cache: Cache, leaf, depth, start_level=0, device="cuda", stream=None):
+        self.cache = cache
+        d = OctreeDesc()
+        d.leaf[:] = [int(x) for x in leaf]
+        d.depth, d.start_level = depth, start_level
+        sz = OctreeSizes()
+        _check(_lib.ro_octree_query(cache.vol.h, ctypes.byref(d), ctypes.byref(sz)), "ro_octree_query")
+        self.sizes = sz
+        self.n_nodes, self.n_leaves = int(sz.n_nodes), int(sz.n_leaves)
+        self.leaf_grid = tuple(int(x) for x in sz.leaf_grid)
+        self.t = {name: _alloc(getattr(sz, name), device) for name in
+                  ("node_meta", "node_mask", "node_flags", "scratch")}
+        b = OctreeBuffers(*[self.t[n].data_ptr() for n in ("node_meta", "node_mask", "node_flags", "scratch")])
+        h = c_vp()
+        _check(_lib.ro_octree_create(cache.h, ctypes.byref(d), ctypes.byref(b), _stream(stream),
+                                     ctypes.byref(h)), "ro_octree_create")
+        self.h = h
+        self.depth = depth
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.ro_octree_destroy(self.h)
+            self.h = None
+
+    def set_leaf_metadata(self, channel: int, leaf_mm: torch.Tensor, stream=None):
+        assert leaf_mm.dtype == torch.uint16 and leaf_mm.is_contiguous()
+        assert leaf_mm.numel() == 2 * self.n_leaves
+        _check(_lib.ro_octree_set_leaf_metadata(self.h, channel, _dev_ptr(leaf_mm), _stream(stream)),
+               "ro_octree_set_leaf_metadata")
+
+    def update_residency(self, stream=None):
+        _check(_lib.ro_update_residency(self.h, _stream(stream)), "ro_update_residency")
+
+    def rebuild_residency(self, stream=None):
+        _check(_lib.ro_rebuild_residency(self.h, _stream(stream)), "ro_rebuild_residency")
+
+    def masks(self) -> np.ndarray:
+        m = self.cache.vol.n_channels
+        return self.t["node_mask"][:2 * self.n_nodes * m].view(torch.int16).cpu().numpy() \
+            .view(np.uint16).reshape(self.n_nodes, m)
+
+    def meta(self) -> np.ndarray:
+        m = self.cache.vol.n_channels
+        a = self.t["node_meta"][:4 * self.n_nodes * m].view(torch.int32).cpu().numpy().view(np.uint32)
+        a = a.reshape(self.n_nodes, m)
+        return np.stack([a & 0xFFFF, a >> 16], axis=-1).astype(np.uint16)
+
+    def render(self, fd: FrameDesc, rgba: torch.Tensor, stream=None):
+        assert rgba.dtype == torch.float32 and rgba.is_contiguous()
+        assert rgba.numel() >= 4 * fd.width * fd.height
+        _check(_lib.ro_render(self.h, ctypes.byref(fd), _dev_ptr(rgba), _stream(stream)), "ro_render")
+
+
+def frame_desc(frame: int, cam: dict, W: int, H: int, step: float, channels: list, tf_dev: torch.Tensor,
+               n_levels: int, term_alpha=0.99, lod_bias=1.0, start_level=-1, flags=0,
+               aov: torch.Tensor = None):
+    """channels: list of {c, lo, hi, W0, W1} in visible-slot order (lo / hi
+    default to the full level range); tf_dev is a device float32 tensor
+    [n_vis][256][4] in the same order."""
+    fd = FrameDesc()
+    fd.frame = frame
+    fd.projection = PROJ_ORTHO if cam["proj"] == "ortho" else PROJ_PERSP
+    fd.eye[:] = cam["eye"]
+    fd.forward[:] = cam["F"]
+    fd.right[:] = cam["R"]
+    fd.up[:] = cam["U"]
+    fd.tx, fd.ty = cam["tx"], cam["ty"]
+    fd.width, fd.height = W, H
+    fd.step, fd.lod_bias = step, lod_bias
+    fd.n_vis = len(channels)
+    for j, ch in enumerate(channels):
+        fd.vis[j] = ch["c"]
+        fd.lod_lo[j] = ch.get("lo", 0)
+        fd.lod_hi[j] = ch.get("hi", n_levels - 1)
+        fd.win_lo[j], fd.win_hi[j] = ch["W0"], ch["W1"]
+    assert tf_dev.dtype == torch.float32 and tf_dev.is_contiguous()
+    assert tf_dev.numel() >= len(channels) * 1024
+    fd.tf_dev = tf_dev.data_ptr()
+    fd.term_alpha = term_alpha
+    fd.start_level = start_level
+    fd.flags = flags | (RENDER_AOV if aov is not None else 0)
+    fd.aov_dev = aov.data_ptr() if aov is not None else None
+    return fd

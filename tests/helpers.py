@@ -38,3 +38,42 @@ def single_sample_camera(point, delta=1000.0):
 def ids_counts(counts: np.ndarray, ids: np.ndarray) -> dict:
     nz = np.nonzero(counts)[0]
     return {int(ids[i]): int(counts[i]) for i in nz}
+
+
+def gpu_rgba(t, H, W):
+    return t.detach().float().cpu().numpy()[: H * W * 4].reshape(H, W, 4).astype(np.float64)
+
+
+def compare_images(gpu, ref, amb_pix, max_abs=1e-3, mean_abs=1e-5, max_amb_frac=1e-3):
+    """Per RGBA channel: max abs <= max_abs and mean abs <= mean_abs over the
+    pixels that are not ambiguous; the ambiguous fraction stays small."""
+    ok = amb_pix == 0
+    frac = 1.0 - ok.mean()
+    d = np.abs(gpu - ref)[ok]
+    mx = d.max(axis=0) if d.size else np.zeros(4)
+    mn = d.mean(axis=0) if d.size else np.zeros(4)
+    assert frac <= max_amb_frac, f"ambiguous pixel fraction {frac}"
+    assert (mx <= max_abs).all(), f"max abs per channel {mx}"
+    assert (mn <= mean_abs).all(), f"mean abs per channel {mn}"
+    return dict(max_abs=mx.tolist(), mean_abs=mn.tolist(), amb_frac=frac)
+
+
+def compare_requests(gpu_ids, gpu_counts, oracle_counts, oracle_amb, dense_ids):
+    """Bit-exact multiset outside the tolerated set: for every brick the GPU
+    count lies in [oracle, oracle + ambiguous samples that requested it]."""
+    g = {int(i): int(c) for i, c in zip(gpu_ids, gpu_counts)}
+    o = ids_counts(oracle_counts, dense_ids)
+    a = ids_counts(oracle_amb, dense_ids)
+    keys = set(g) | set(o)
+    bad = [(hex(k), g.get(k, 0), o.get(k, 0), a.get(k, 0)) for k in sorted(keys)
+           if not (o.get(k, 0) <= g.get(k, 0) <= o.get(k, 0) + a.get(k, 0))]
+    assert not bad, f"{len(bad)} request counts differ, first: {bad[:8]}"
+    return len(g)
+
+
+def compare_usage(gpu_slots, oracle_used, oracle_amb_used):
+    g = set(int(s) for s in gpu_slots)
+    o = set(np.nonzero(oracle_used)[0].tolist())
+    a = set(np.nonzero(oracle_amb_used)[0].tolist())
+    assert o <= g, f"slots read by the oracle but not the GPU: {sorted(o - g)[:8]}"
+    assert g <= o | a, f"slots read by the GPU only: {sorted(g - o - a)[:8]}"

@@ -1,0 +1,209 @@
+"""GPU parity of the render path against the CPU oracle (through the C ABI).
+
+Images: per RGBA channel <= 1e-3 max abs and <= 1e-5 mean abs over the
+pixels that are not ambiguous.  Requests (multiset), usage (slot set), page
+tables and masks: bit-exact outside the oracle's tolerated set."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import (compare_images, compare_requests, compare_usage, gpu_rgba, leaf_grid)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2309_04393_amd.pipeline import GpuScene  # noqa: E402
+
+
+def _report(name, **kw):
+    print(f"[{name}] " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+class Pair:
+    """A GPU scene and the oracle's view of the same inputs."""
+
+    def __init__(self, src, B, leaf, depth, n_slots, max_batch=1024, start_level=0):
+        self.src = src
+        self.gpu = GpuScene(src, B, leaf, depth, n_slots, max_batch=max_batch, start_level=start_level)
+        self.V = oracle.make_volume(src.dims, src.spacing, src.n_channels, src.bits, B, src.n_levels, leaf,
+                                    depth)
+        self.sim = oracle.CacheSim(self.V, n_slots)
+        self.ids = oracle.dense_ids(self.V)
+        lg = leaf_grid(src.dims, leaf, depth)
+        self.leaf_mm = np.stack([src.leaf_minmax(c, leaf, lg) for c in range(src.n_channels)])
+        self.S = n_slots
+
+    def upload(self, frame, ids):
+        fg = self.gpu.upload(frame, ids)
+        fo, ev, so = self.sim.stream(frame, self.sim.dense_of(ids))
+        assert np.array_equal(fg, fo), "upload flags differ"
+        pt_gpu = self.gpu.cache.page_table_host()
+        dev_pt = self.gpu.cache.t["page_table"][:4 * len(pt_gpu)].view(torch.int32).cpu().numpy().view(np.uint32)
+        assert np.array_equal(dev_pt, pt_gpu), "device page table differs from the host mirror"
+        return fg
+
+    def check_page_table(self):
+        pt = self.gpu.cache.page_table_host()
+        all_ids = self.gpu.all_ids()
+        gmap = {int(i): int(s) for i, s in zip(all_ids, pt) if s != 0xFFFFFFFF}
+        assert gmap == self.sim.page_table(), "page tables differ"
+
+    def check_masks(self):
+        self.gpu.tree.update_residency()
+        torch.cuda.synchronize()
+        m_gpu = self.gpu.tree.masks()
+        m_or = oracle.masks(self.V, self.sim.res_slot)
+        assert np.array_equal(m_gpu, m_or), f"masks differ at {np.argwhere(m_gpu != m_or)[:5]}"
+
+    def frame(self, f, cam, W, H, step, chans, term_margin=1e-5, aov=False, **kw):
+        r = self.gpu.render(f, cam, W, H, step, chans, aov=aov, **kw)
+        torch.cuda.synchronize()
+        ids, cnt, nu, tot = self.gpu.cache.read_requests(1 << 20)
+        used, nused = self.gpu.cache.read_usage(f)
+        fr, keep = oracle.make_frame(cam, W, H, step, chans, term_margin=term_margin,
+                                     lod_bias=kw.get("lod_bias", 1.0))
+        o = oracle.render(self.V, self.src.levels, self.sim.res_slot, self.leaf_mm, fr, self.S, aov=aov)
+        self.sim.touch(f, o["used"])
+        out = dict(gpu=gpu_rgba(r["rgba"], H, W), ref=o["rgba"], o=o, ids=ids, cnt=cnt, nu=nu, tot=tot,
+                   used=used, r=r)
+        if aov:
+            out["aov"] = r["aov"].cpu().numpy().reshape(H, W, self.src.n_levels)
+        return out
+
+    def check_frame(self, res, name):
+        st = compare_images(res["gpu"], res["ref"], res["o"]["amb_pix"])
+        nreq = compare_requests(res["ids"], res["cnt"], res["o"]["counts"], res["o"]["amb_counts"], self.ids)
+        compare_usage(res["used"], res["o"]["used"], res["o"]["amb_used"])
+        _report(name, requests=nreq, total=res["tot"], used=len(res["used"]), **st,
+                samples=res["o"]["stats"]["samples"])
+        return st
+
+
+def _cfg1_chans(lo=0, hi=2):
+    W0, W1 = synth.window_fx(0.05 * 255, 255)
+    return [dict(c=0, lo=lo, hi=hi, W0=W0, W1=W1, tf=synth.tf_ramp())]
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return synth.config1_volume()
+
+
+def test_cfg1_full_resident_axis_view(cfg1):
+    p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
+    ids = p.gpu.all_ids()
+    assert (p.upload(0, ids) == 1).all()
+    p.check_page_table()
+    p.check_masks()
+    cam = synth.camera_ortho_axis((64, 64), 128, 128)
+    res = p.frame(1, cam, 128, 128, 0.5, _cfg1_chans(0, 0), term_margin=2e-6, aov=True)
+    p.check_frame(res, "cfg1-axis")
+    assert res["tot"] == 0
+    assert np.array_equal(res["aov"], res["o"]["aov"]) or (res["o"]["amb_pix"].any())
+    # brute force at full resolution (all L0 resident)
+    fr, keep = oracle.make_frame(cam, 128, 128, 0.5, _cfg1_chans(0, 0))
+    b = oracle.brute(p.V, cfg1.levels, 0, fr)
+    compare_images(res["gpu"], b, res["o"]["amb_pix"])
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_cfg1_partial_residency_oblique(cfg1, seed):
+    rng = np.random.default_rng(seed)
+    p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
+    ids = p.gpu.all_ids()
+    pick = ids[rng.random(len(ids)) < 0.45]
+    rng.shuffle(pick)
+    p.upload(0, pick)
+    p.check_page_table()
+    p.check_masks()
+    cam = synth.camera_oblique_ortho((64, 64, 64), (1, 1, 1), seed, 96, 80)
+    res = p.frame(1, cam, 96, 80, 0.5, _cfg1_chans(0, 2), aov=True)
+    p.check_frame(res, f"cfg1-partial-{seed}")
+    amb = res["o"]["amb_pix"] == 0
+    assert np.array_equal(res["aov"][amb], res["o"]["aov"][amb])
+
+
+def test_cfg1_substitution_levels(cfg1):
+    """Only level-2 bricks (and a few level-1) resident, desired level 0:
+    every sample uses the finest resident coarser level."""
+    p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=20)
+    ids = p.gpu.all_ids(levels=[2]).tolist() + p.gpu.all_ids(levels=[1]).tolist()[:3]
+    p.upload(0, ids)
+    p.check_masks()
+    cam = synth.camera_ortho_axis((64, 64), 128, 128)
+    res = p.frame(1, cam, 128, 128, 0.5, _cfg1_chans(0, 0), term_margin=2e-6, aov=True)
+    p.check_frame(res, "cfg1-substitution")
+    assert res["aov"][..., 0].sum() == 0
+    assert res["aov"][..., 1].sum() > 0 and res["aov"][..., 2].sum() > 0
+
+
+def test_skip_and_start_level_change_nothing(cfg1):
+    p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
+    rng = np.random.default_rng(7)
+    ids = p.gpu.all_ids()
+    p.upload(0, ids[rng.random(len(ids)) < 0.6])
+    p.gpu.tree.update_residency()
+    cam = synth.camera_oblique_ortho((64, 64, 64), (1, 1, 1), 11, 96, 96)
+    outs = []
+    from paper_2309_04393_amd import resoct
+    for f, (flags, sl) in enumerate([(resoct.RENDER_NO_SKIP, -1), (0, 0), (0, 1), (0, 2), (0, 3)]):
+        r = p.gpu.render(1 + f, cam, 96, 96, 0.5, _cfg1_chans(0, 2), flags=flags, start_level=sl)
+        torch.cuda.synchronize()
+        ids_, cnt, nu, tot = p.gpu.cache.read_requests(1 << 20)
+        used, _ = p.gpu.cache.read_usage(1 + f)
+        outs.append((r["rgba"].cpu().numpy().copy(), ids_.copy(), cnt.copy(), np.sort(used)))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]), "image changed"
+        assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2]), "requests changed"
+        assert np.array_equal(o[3], outs[0][3]), "usage changed"
+
+
+def test_cfg1_perspective(cfg1):
+    p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
+    rng = np.random.default_rng(4)
+    ids = p.gpu.all_ids()
+    p.upload(0, ids[rng.random(len(ids)) < 0.7])
+    p.check_masks()
+    cam = synth.camera_persp((120.0, 95.0, 80.0), (32, 30, 34), (0, 0, 1), 50.0, 1.25)
+    res = p.frame(1, cam, 100, 80, 0.5, _cfg1_chans(0, 2), lod_bias=0.6, aov=True)
+    p.check_frame(res, "cfg1-persp")
+    assert (res["aov"].sum(axis=(0, 1)) > 0).sum() >= 2  # several levels in use
+
+
+def test_multichannel_ragged_u16():
+    src = synth.BlobVolume((40, 24, 20), n_channels=3, bits=16, n_levels=3, seed=21, spacing=(1, 1, 2))
+    p = Pair(src, 8, (4, 4, 4), 4, n_slots=60, max_batch=64)
+    rng = np.random.default_rng(2)
+    ids = p.gpu.all_ids()
+    rng.shuffle(ids)
+    p.upload(0, ids[: len(ids) // 2])
+    p.upload(1, ids[len(ids) // 2:])  # more than the cache holds: evictions
+    p.check_page_table()
+    p.check_masks()
+    chans = [dict(c=c, lo=0, hi=2, W0=3000 * 256, W1=60000 * 256, tf=synth.tf_hue(c / 3.0, 0.3))
+             for c in (2, 0, 1)]
+    cam = synth.camera_persp((70.0, -30.0, 60.0), (20, 12, 20), (0, 0, 1), 45.0, 1.0)
+    res = p.frame(2, cam, 64, 64, 0.5, chans, lod_bias=0.8, aov=True)
+    p.check_frame(res, "ragged-3ch")
+
+
+def test_cells_reduced_config2():
+    src = synth.CellVolume((256, 256, 64), 4, spacing=(1, 1, 4), n_levels=5, seed=2)
+    src.levels = [[src.level_array(c, l) for l in range(src.n_levels)] for c in range(4)]
+    p = Pair(src, 32, (16, 16, 4), 4, n_slots=200, max_batch=512)
+    ids = p.gpu.all_ids()
+    rng = np.random.default_rng(3)
+    rng.shuffle(ids)
+    p.upload(0, ids[:150])
+    p.check_page_table()
+    p.check_masks()
+    chans = [dict(c=c, lo=0, hi=4, W0=300 * 256, W1=8000 * 256, tf=synth.tf_hue(c / 4.0, 0.1)) for c in range(4)]
+    cams = synth.orbit_path(src.dims, src.spacing, 2)
+    res = p.frame(1, cams[1], 128, 128, 0.5, chans, aov=True)
+    p.check_frame(res, "cells-4ch")
