@@ -1,0 +1,387 @@
+#!/usr/bin/env python3
+"""Benchmark of the residency-octree hot path on one MI355X.
+
+One step = one frame of the whole path: ray casting over the residency
+octree (traversal, empty-space skipping, desired level, page-table lookup,
+substitution, trilinear sampling, per-channel transfer functions, channel
+mix, front-to-back compositing, request and usage recording), request
+compaction and readback, the plain request-driven upload policy, the LRU
+streaming batch (slot choice, page-table update, brick scatter) and the
+residency-octree update.
+
+Workload (default): 16 channels of uint16, 8192 x 8192 x 192 voxels
+(z spacing 3), Poisson-placed cells under a low-frequency tissue mask,
+32^3 bricks with a one-voxel halo, 9 levels, 16 GiB brick cache, a
+1920 x 1080 perspective fly-through (300 frames) from the whole slide down
+to single cells; the timed frames sit mid-path at about one voxel per pixel.
+
+Inputs are resident in HBM when the timed region starts: the cache is warmed
+along the path with bricks from the host generator (the data server), then
+the K timed frames are run once untimed from a device-side checkpoint to
+collect the bricks they will upload, the checkpoint is restored, and the same
+K frames are timed with those bricks already in device memory.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "samples/s & ms/frame @1080p 16ch; HBM GB/s; frames-to-converge; p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def config(name):
+    import synth
+    if name == "cfg3":
+        vol = synth.config3_volume()
+        return dict(name="16ch-8192x8192x192-u16-1080p", vol=vol, B=32, leaf=(16, 16, 8), depth=9,
+                    n_slots=218551, U=2048, W=1920, H=1080, n_frames=300, f0=150, start_level=2,
+                    path="fly", seed=3)
+    if name == "cfg2":
+        vol = synth.config2_volume()
+        return dict(name="4ch-2048x2048x64-u16-1024p", vol=vol, B=32, leaf=(16, 16, 4), depth=7,
+                    n_slots=27318, U=512, W=1024, H=1024, n_frames=120, f0=60, start_level=2,
+                    path="orbit", seed=2)
+    raise SystemExit(f"unknown config {name}")
+
+
+def channels(n, seed):
+    import synth
+    rng = np.random.default_rng(seed + 100)
+    out = []
+    for c in range(n):
+        j = rng.uniform(0.8, 1.2, 2)
+        W0, W1 = synth.window_fx(300 * j[0], 8000 * j[1])
+        out.append(dict(c=c, lo=0, W0=W0, W1=W1, tf=synth.tf_hue(c / n, 0.1)))
+    return out
+
+
+def tissue_target(vol, seed):
+    import synth
+    rng = np.random.default_rng(seed + 7)
+    L = synth.lib()
+    for _ in range(10000):
+        x, y = rng.uniform(0.25, 0.75, 2) * np.array(vol.dims[:2])
+        if L.synth_tissue(vol._ctx, float(x), float(y)) > 0.95:
+            return (x * vol.spacing[0], y * vol.spacing[1], vol.dims[2] * vol.spacing[2] / 2)
+    return tuple(np.array(vol.dims) * np.array(vol.spacing) / 2)
+
+
+class Frames:
+    """Frame loop over the GPU scene (plain request-driven streaming)."""
+
+    def __init__(self, scene, cams, chans, W, H, U, step):
+        import torch
+        self.torch = torch
+        self.s = scene
+        self.cams = cams
+        self.chans = chans
+        self.W, self.H, self.U, self.step = W, H, U, step
+        self.tf = scene.tf_tensor(chans)
+        self.out = torch.empty(W * H * 4, dtype=torch.float32, device="cuda")
+        self.stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+
+    def render(self, f, cam_index=None):
+        return self.s.render(f, self.cams[f if cam_index is None else cam_index], self.W, self.H,
+                             self.step, self.chans, tf_dev=self.tf, out=self.out,
+                             stats=self.stats)
+
+    def plan(self, cap=1 << 20):
+        ids, cnt, nu, tot = self.s.cache.read_requests(cap)
+        order = np.lexsort((ids, -cnt.astype(np.int64)))  # count desc, id asc
+        return ids[order][: self.U], tot, nu
+
+    def step_frame(self, f, staged=None):
+        """One full step; returns (upload ids, staged tensor, missing)."""
+        self.render(f)
+        ids, tot, nu = self.plan()
+        if staged is None:
+            staged = self.s.stage(ids) if len(ids) else None
+        if len(ids):
+            self.s.cache.stream_bricks(f, ids, staged)
+        self.s.tree.update_residency()
+        return ids, staged, tot
+
+
+def snapshot(scene):
+    import torch
+    dev = {("c", k): v.clone() for k, v in scene.cache.t.items() if k != "scratch"}
+    dev.update({("t", k): v.clone() for k, v in scene.tree.t.items() if k != "scratch"})
+    torch.cuda.synchronize()
+    return dev, scene.cache.save_state()
+
+
+def restore(scene, snap):
+    import torch
+    dev, host = snap
+    for (kind, k), v in dev.items():
+        (scene.cache.t if kind == "c" else scene.tree.t)[k].copy_(v)
+    torch.cuda.synchronize()
+    scene.cache.load_state(host)
+
+
+def cpu_baseline(cfg, scene, cams, chans, f, step, tile):
+    """The oracle on a tile x tile pixel window of frame f, every brick
+    resident (samples read their desired level), level data materialised
+    for the window's rays from the generator."""
+    import oracle
+    vol = cfg["vol"]
+    W, H = cfg["W"], cfg["H"]
+    cam = cams[f]
+    x0, y0 = (W - tile) // 2, (H - tile) // 2
+    # bounding box of the tile's rays inside the volume (edge pixels)
+    V = oracle.make_volume(vol.dims, vol.spacing, vol.n_channels, 16, cfg["B"], vol.n_levels, cfg["leaf"],
+                           cfg["depth"])
+    eye = np.array(cam["eye"]) / np.array(vol.spacing)
+    lo = np.full(3, np.inf)
+    hi = np.full(3, -np.inf)
+    edge = [(i, y0) for i in range(x0, x0 + tile)] + [(i, y0 + tile - 1) for i in range(x0, x0 + tile)] + \
+           [(x0, j) for j in range(y0, y0 + tile)] + [(x0 + tile - 1, j) for j in range(y0, y0 + tile)]
+    dims = np.array(vol.dims, dtype=np.float64)
+    for (i, j) in edge:
+        a = (2 * i + 1 - W) / W
+        b = (H - 2 * j - 1) / H
+        d = np.array(cam["F"]) + a * cam["tx"] * np.array(cam["R"]) + b * cam["ty"] * np.array(cam["U"])
+        d = d / np.linalg.norm(d) / np.array(vol.spacing)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t0 = np.where(d != 0, (0 - eye) / d, -np.inf)
+            t1 = np.where(d != 0, (dims - eye) / d, np.inf)
+        ta, tb = np.max(np.minimum(t0, t1)), np.min(np.maximum(t0, t1))
+        if ta > tb:
+            continue
+        for t in (ta, tb):
+            p = eye + t * d
+            lo = np.minimum(lo, p)
+            hi = np.maximum(hi, p)
+    lo = np.clip(np.floor(lo) - 2, 0, dims - 1).astype(int)
+    hi = np.clip(np.ceil(hi) + 2, 1, dims).astype(int)
+    ldims, lf, _ = oracle.level_info(V)
+    levels, boxes = [], np.zeros((vol.n_channels, vol.n_levels, 6), np.int32)
+    need = 2  # levels materialised (the timed frames read levels 0-1)
+    per_level = []
+    for l in range(vol.n_levels):
+        if l >= need:
+            per_level.append(None)
+            continue
+        a = lo // lf[l]
+        b = np.minimum(-(-hi // lf[l]) + 1, ldims[l])
+        reg = vol.region(l, int(a[0]), int(a[1]), int(a[2]), int(b[0] - a[0]), int(b[1] - a[1]),
+                         int(b[2] - a[2]))
+        per_level.append((reg, a, b - a))
+    for c in range(vol.n_channels):
+        row = []
+        for l in range(vol.n_levels):
+            if per_level[l] is None:
+                row.append(np.zeros((1, 1, 1), np.uint16))
+                boxes[c, l] = [0, 0, 0, 1, 1, 1]
+            else:
+                reg, a, n = per_level[l]
+                row.append(np.ascontiguousarray(reg[c]))
+                boxes[c, l] = [a[0], a[1], a[2], n[0], n[1], n[2]]
+        levels.append(row)
+    lm = scene_leaf_mm(cfg, V)
+    res = np.arange(oracle.brick_count(V), dtype=np.int32)
+    fr, keep = oracle.make_frame(cam, W, H, step, [dict(ch, hi=vol.n_levels - 1) for ch in chans])
+    # restrict to the tile: render rows y0..y0+tile of a frame cropped to the tile's columns by
+    # shifting the camera window: use the row band and ignore columns outside the tile
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    fr2, keep2 = oracle.make_frame(sub_camera(cam, W, H, x0, y0, tile), tile, tile, step,
+                                   [dict(ch, hi=vol.n_levels - 1) for ch in chans])
+    t = time.perf_counter()
+    r = oracle.render(V, levels, res, lm, fr2, 1, n_threads=threads, boxes=boxes)
+    dt = time.perf_counter() - t
+    assert not np.isnan(r["rgba"]).any(), "oracle sampled outside the materialised window"
+    s = r["stats"]["samples"]
+    return dict(value=s / dt, unit="samples/s", cores=threads, kind="oracle",
+                sample=f"{tile}x{tile}-pixel window at the centre of timed frame {f}, all bricks resident, "
+                       f"{s} ray samples x {len(chans)} channels in {dt:.1f} s"), r
+
+
+def sub_camera(cam, W, H, x0, y0, n):
+    """Camera whose n x n image is the window [x0, x0+n) x [y0, y0+n) of the
+    W x H image of `cam` (same rays: perspective only)."""
+    assert cam["proj"] == "persp"
+    # pixel i of the window = pixel x0 + i of the full image:
+    # a_full = (2 (x0+i) + 1 - W) / W = ((2i + 1 - n) / n) * (n / W) + (2 x0 + n - W) / W
+    F = np.array(cam["F"]) + ((2 * x0 + n - W) / W) * cam["tx"] * np.array(cam["R"]) + \
+        ((H - 2 * y0 - n) / H) * cam["ty"] * np.array(cam["U"])
+    return dict(proj="persp", eye=cam["eye"], F=list(F), R=cam["R"], U=cam["U"], tx=cam["tx"] * n / W,
+                ty=cam["ty"] * n / H)
+
+
+_LM = {}
+
+
+def leaf_grid(dims, leaf, depth):
+    n = []
+    for a in range(3):
+        nl = -(-dims[a] // leaf[a])
+        s = 0
+        while (1 << s) < nl:
+            s += 1
+        n.append(1 << s)
+    return tuple(n)
+
+
+def leaf_mm_all(cfg):
+    key = cfg["name"]
+    if key not in _LM:
+        vol = cfg["vol"]
+        lg = leaf_grid(vol.dims, cfg["leaf"], cfg["depth"])
+        mx = vol.leaf_max_all(cfg["leaf"], lg)
+        mm = np.zeros((vol.n_channels, mx.shape[1], 2), np.uint16)
+        mm[:, :, 1] = mx
+        _LM[key] = mm
+    return _LM[key]
+
+
+def scene_leaf_mm(cfg, V=None):
+    return leaf_mm_all(cfg)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="cfg3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", type=int, default=192)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_2309_04393_amd.pipeline import GpuScene
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    cfg = config(args.config)
+    vol = cfg["vol"]
+    t_setup = time.perf_counter()
+    scene = GpuScene(vol, cfg["B"], cfg["leaf"], cfg["depth"], cfg["n_slots"], max_batch=cfg["U"],
+                     start_level=cfg["start_level"], set_metadata=False)
+    mm = leaf_mm_all(cfg)
+    for c in range(vol.n_channels):
+        scene.set_metadata(c, mm[c])
+    log(f"scene ready: {scene.cache.n_bricks} bricks, {scene.tree.n_nodes} nodes, "
+        f"{cfg['n_slots']} slots x {scene.cache.slot_stride} B ({time.perf_counter() - t_setup:.1f} s)")
+    if cfg["path"] == "fly":
+        cams = synth.flythrough_path(vol.dims, vol.spacing, cfg["n_frames"], tissue_target(vol, cfg["seed"]))
+    else:
+        cams = synth.orbit_path(vol.dims, vol.spacing, cfg["n_frames"])
+    chans = [dict(ch, hi=vol.n_levels - 1) for ch in channels(vol.n_channels, cfg["seed"])]
+    step = 0.5 * min(vol.spacing)
+    K, Wm = args.steps, args.warmup
+    f0 = cfg["f0"]
+    fl = Frames(scene, cams, chans, cfg["W"], cfg["H"], cfg["U"], step)
+    # bulk warm-up on the first warm-up frame: the visible working set resident
+    fw = f0 - Wm
+    for it in range(4):
+        fl.render(fw)
+        ids, cnt, nu, tot = scene.cache.read_requests(1 << 22)
+        log(f"bulk warm {it}: {nu} bricks requested, {tot} missing samples")
+        if nu == 0:
+            break
+        t = time.perf_counter()
+        scene.upload(fw, ids)
+        scene.tree.update_residency()
+        torch.cuda.synchronize()
+        log(f"  uploaded {len(ids)} bricks in {time.perf_counter() - t:.1f} s")
+    for f in range(fw, f0):
+        ids, _, tot = fl.step_frame(f)
+        log(f"warm-up frame {f}: {tot} missing samples, {len(ids)} uploads")
+    torch.cuda.synchronize()
+    snap = snapshot(scene)
+    # pass A: collect the uploads of the timed frames (untimed)
+    plans, store, usage, stats_a = [], [], [], []
+    for f in range(f0, f0 + K):
+        fl.stats.zero_()
+        ids, staged, tot = fl.step_frame(f)
+        plans.append(ids.copy())
+        store.append(staged)
+        _, nused = scene.cache.read_usage(f)
+        usage.append(nused)
+        stats_a.append(fl.stats.cpu().numpy().copy())
+        log(f"pass A frame {f}: {tot} missing samples, {len(ids)} uploads, {nused} slots read, "
+            f"stats {stats_a[-1].tolist()}")
+    restore(scene, snap)
+    del snap
+    # pass B: timed
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    fl.stats.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, f in enumerate(range(f0, f0 + K)):
+        ev[i][0].record()
+        fl.render(f)
+        ev[i][1].record()
+        ids, tot, nu = fl.plan()
+        if not np.array_equal(ids, plans[i]):
+            raise SystemExit(f"frame {f}: the timed pass planned other uploads than the collection pass")
+        if len(ids):
+            scene.cache.stream_bricks(f, ids, store[i])
+        scene.tree.update_residency()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = fl.stats.cpu().numpy()
+    render_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_step = (t1 - t0) * 1000.0 / K
+    samples = int(st[0])
+    ch_samples = int(st[1])
+    slot_bytes = (cfg["B"] + 2) ** 3 * 2
+    alg_bytes = [u * slot_bytes + cfg["W"] * cfg["H"] * 16 for u in usage]
+    mean_render_s = np.mean(render_ms) / 1000.0
+    achieved = np.mean(alg_bytes) / mean_render_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": samples / (t1 - t0),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "frames": f"{f0}..{f0 + K - 1} of {cfg['n_frames']}",
+                   "image": [cfg["W"], cfg["H"]], "channels": vol.n_channels, "cache_slots": cfg["n_slots"],
+                   "upload_budget": cfg["U"], "parallelism": "1 GPU"},
+        "render_ms": float(np.mean(render_ms)),
+        "channel_samples_per_s": ch_samples / (t1 - t0),
+        "render_samples_per_s": samples / (np.sum(render_ms) / 1000.0),
+        "uploads_per_frame": float(np.mean([len(p) for p in plans])),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_render", "alg_bytes_per_launch": float(np.mean(alg_bytes))},
+    }
+    if not args.no_cpu_baseline:
+        try:
+            cb, _ = cpu_baseline(cfg, scene, cams, chans, f0, step, args.tile)
+            out["cpu_baseline"] = cb
+        except Exception as e:  # reported, not fatal
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -165,6 +165,17 @@ ro_status ro_read_usage(ro_cache *c, uint32_t frame, uint32_t cap, uint32_t *slo
  * (0xFFFFFFFF when not resident), `count` entries from ro_volume_brick_count. */
 ro_status ro_cache_page_table_host(const ro_cache *c, uint32_t *out, uint64_t count);
 
+/* Host-side state of a cache: page-table and slot-map mirrors, bricks
+ * awaiting a residency update, upload counter.  Together with copies of the
+ * caller-owned device buffers (page table, counters, slot map, stamps, seqs,
+ * slots, node masks and metadata) it is a complete checkpoint: save, later
+ * copy the device buffers back and load, and the cache continues exactly as
+ * from the save point.  save/load do not touch device memory. */
+ro_status ro_cache_state_size(const ro_cache *c, size_t *bytes);
+ro_status ro_cache_save_state(const ro_cache *c, void *host, size_t cap);
+/* RO_E_ARG if the blob was saved from a cache of another shape. */
+ro_status ro_cache_load_state(ro_cache *c, const void *host, size_t size);
+
 /* ---------------------------------------------------------------- octree */
 
 /* Residency octree (Sec. 5.2): a full pointerless tree over the L0 domain
@@ -275,6 +286,9 @@ typedef struct {
     int32_t start_level;  /* traversal start level (Sec. 6, implementation), -1: the octree's */
     uint32_t flags;       /* RO_RENDER_* */
     uint32_t *aov_dev;    /* RO_RENDER_AOV: device [H][W][k] uint32, zeroed by the caller */
+    unsigned long long *stats_dev; /* optional device [4], accumulated (not cleared): ray samples
+                                      evaluated, channel samples read from bricks, channel samples
+                                      whose desired brick was missing, leaf visits */
 } ro_frame_desc;
 
 /* Renders into rgba_dev[H][W][4] (float, premultiplied) and updates the

@@ -86,8 +86,8 @@ def lib():
         L.or_tf_empty.restype = ci
         L.or_tf_empty.argtypes = [ctypes.c_uint32] * 4 + [vp]
         L.or_render.restype = ci
-        L.or_render.argtypes = [PV, vp, vp, vp, ctypes.POINTER(Frame), vp, vp, vp, vp, vp, vp, vp,
-                                ctypes.POINTER(Stats), ci]
+        L.or_render.argtypes = [PV, vp, vp, vp, vp, vp, ctypes.POINTER(Frame), ci, ci, vp, vp, vp, vp,
+                                vp, vp, vp, ctypes.POINTER(Stats), ci]
         L.or_brute.restype = ci
         L.or_brute.argtypes = [PV, vp, ci, ctypes.POINTER(Frame), vp]
         L.or_plain_policy.restype = ci
@@ -214,10 +214,28 @@ def _level_ptrs(V: Volume, levels):
     return ptrs, arrs
 
 
+class Source(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("fetch", ctypes.c_void_p)]
+
+
+def source_from_generator(gen):
+    """Voxel source backed by the generator's region query (for volumes
+    too large to hold as level arrays)."""
+    import synth
+    s = Source()
+    s.ctx = gen._ctx
+    s.fetch = ctypes.cast(synth.lib().synth_cells_region, ctypes.c_void_p).value
+    return s
+
+
 def render(V: Volume, levels, res_slot, leaf_mm, frame: Frame, n_slots: int, aov=False,
-           n_threads=0):
+           n_threads=0, source: Source = None, rows=None, boxes=None):
     """O1.  Returns dict with rgba [H][W][4] f64, counts [dense] u32,
-    used [slots] u8, amb_pix, amb_counts, amb_used, aov, stats."""
+    used [slots] u8, amb_pix, amb_counts, amb_used, aov, stats.  With
+    `source` (and levels None) voxels come from the generator; `rows`
+    = (row0, row1) restricts the frame to a band of rows; `boxes`
+    [C][L][6] (origin, size) says that levels[c][l] holds only that window
+    of the level (samples outside it read NaN)."""
     W, H = frame.W, frame.H
     nb = brick_count(V)
     rgba = np.zeros((H, W, 4), np.float64)
@@ -227,11 +245,17 @@ def render(V: Volume, levels, res_slot, leaf_mm, frame: Frame, n_slots: int, aov
     amb_counts = np.zeros(nb, np.uint32)
     amb_used = np.zeros(max(n_slots, 1), np.uint8)
     aov_a = np.zeros((H, W, V.n_levels), np.uint32) if aov else None
-    ptrs, keep = _level_ptrs(V, levels)
+    if levels is not None:
+        ptrs, keep = _level_ptrs(V, levels)
+    else:
+        ptrs, keep = None, None
     rs = np.ascontiguousarray(res_slot, dtype=np.int32)
     lm = np.ascontiguousarray(leaf_mm, dtype=np.uint16)
     st = Stats()
-    rc = lib().or_render(ctypes.byref(V), ptrs, _p(rs), _p(lm), ctypes.byref(frame), _p(rgba),
+    r0, r1 = rows if rows is not None else (0, 0)
+    bx = None if boxes is None else np.ascontiguousarray(boxes, dtype=np.int32)
+    rc = lib().or_render(ctypes.byref(V), ptrs, _p(bx), ctypes.byref(source) if source is not None else None,
+                         _p(rs), _p(lm), ctypes.byref(frame), r0, r1, _p(rgba),
                          _p(counts), _p(used), _p(aov_a), _p(amb_pix), _p(amb_counts),
                          _p(amb_used), ctypes.byref(st), n_threads)
     assert rc == 0

@@ -347,22 +347,81 @@ typedef struct {
 } or_frame;
 
 /* Level data: lvl[c * L + l] points to the level's array [z][y][x]
- * (uint8 or uint16 per V->bits). */
+ * (uint8 or uint16 per V->bits).  When lvl is NULL the voxels come from a
+ * data source instead (the generator's region query) through a small
+ * per-thread tile cache; the values are the same, only the access differs. */
 
-static inline double voxel(const or_volume *V, const void *a, const int d[3], int x, int y, int z) {
+typedef int (*or_fetch_fn)(void *ctx, const int f[3], int x0, int y0, int z0, int nx, int ny, int nz,
+                           int nchan, const int *chans, uint16_t *out);
+
+typedef struct {
+    void *ctx;
+    or_fetch_fn fetch;
+} or_source;
+
+#define TILE 16
+#define TCACHE 64
+
+typedef struct {
+    int key[5]; /* c, l, tx, ty, tz; c = -1 when empty */
+    uint16_t v[TILE * TILE * TILE];
+} tile_t;
+
+typedef struct {
+    const or_volume *V;
+    const void *const *lvl;
+    const int *box; /* optional [C*L][6]: window origin and size of each level array */
+    const or_source *src;
+    tile_t *tiles; /* TCACHE entries, this thread's */
+    const int (*dl)[3];
+    const int (*f)[3];
+    int L;
+} sampler_t;
+
+static inline double voxel(const sampler_t *S, int c, int l, int x, int y, int z) {
+    const int *d = S->dl[l];
     if (x < 0) x = 0;
     if (y < 0) y = 0;
     if (z < 0) z = 0;
     if (x > d[0] - 1) x = d[0] - 1;
     if (y > d[1] - 1) y = d[1] - 1;
     if (z > d[2] - 1) z = d[2] - 1;
-    size_t i = ((size_t)z * d[1] + y) * d[0] + x;
-    return V->bits == 8 ? (double)((const uint8_t *)a)[i] : (double)((const uint16_t *)a)[i];
+    if (S->lvl) {
+        const void *a = S->lvl[c * S->L + l];
+        size_t i;
+        if (S->box) {
+            /* the array holds only a window of the level */
+            const int *w = S->box + 6 * (c * S->L + l);
+            int X = x - w[0], Y = y - w[1], Z = z - w[2];
+            if (X < 0 || Y < 0 || Z < 0 || X >= w[3] || Y >= w[4] || Z >= w[5]) return NAN;
+            i = ((size_t)Z * w[4] + Y) * w[3] + X;
+        } else {
+            i = ((size_t)z * d[1] + y) * d[0] + x;
+        }
+        return S->V->bits == 8 ? (double)((const uint8_t *)a)[i] : (double)((const uint16_t *)a)[i];
+    }
+    int tx = x / TILE, ty = y / TILE, tz = z / TILE;
+    unsigned h = ((unsigned)c * 73856093u) ^ ((unsigned)l * 19349663u) ^ ((unsigned)tx * 83492791u) ^
+                 ((unsigned)ty * 2654435761u) ^ ((unsigned)tz * 40503u);
+    tile_t *t = &S->tiles[h % TCACHE];
+    if (!(t->key[0] == c && t->key[1] == l && t->key[2] == tx && t->key[3] == ty && t->key[4] == tz)) {
+        int x0 = tx * TILE, y0 = ty * TILE, z0 = tz * TILE;
+        int nx = d[0] - x0 < TILE ? d[0] - x0 : TILE;
+        int ny = d[1] - y0 < TILE ? d[1] - y0 : TILE;
+        int nz = d[2] - z0 < TILE ? d[2] - z0 : TILE;
+        uint16_t buf[TILE * TILE * TILE];
+        S->src->fetch(S->src->ctx, S->f[l], x0, y0, z0, nx, ny, nz, 1, &c, buf);
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) t->v[(k * TILE + j) * TILE + i] = buf[(k * ny + j) * nx + i];
+        t->key[0] = c; t->key[1] = l; t->key[2] = tx; t->key[3] = ty; t->key[4] = tz;
+    }
+    return (double)t->v[((z - tz * TILE) * TILE + (y - ty * TILE)) * TILE + (x - tx * TILE)];
 }
 
-/* Trilinear interpolation in a level array at level coordinates q (voxel
- * i centred at i + 1/2; clamp-to-edge indices). */
-static double trilinear(const or_volume *V, const void *a, const int d[3], const double q[3]) {
+/* Trilinear interpolation in level l of channel c at level coordinates q
+ * (voxel i centred at i + 1/2; clamp-to-edge indices). */
+static double trilinear(const sampler_t *S, int c, int l, const double q[3]) {
     int i0[3];
     double w[3];
     for (int k = 0; k < 3; ++k) {
@@ -371,16 +430,23 @@ static double trilinear(const or_volume *V, const void *a, const int d[3], const
         i0[k] = (int)fl;
         w[k] = p - fl;
     }
-    double c[2][2];
+    double cc[2][2];
     for (int dz = 0; dz < 2; ++dz)
         for (int dy = 0; dy < 2; ++dy) {
-            double v0 = voxel(V, a, d, i0[0], i0[1] + dy, i0[2] + dz);
-            double v1 = voxel(V, a, d, i0[0] + 1, i0[1] + dy, i0[2] + dz);
-            c[dz][dy] = v0 * (1.0 - w[0]) + v1 * w[0];
+            double v0 = voxel(S, c, l, i0[0], i0[1] + dy, i0[2] + dz);
+            double v1 = voxel(S, c, l, i0[0] + 1, i0[1] + dy, i0[2] + dz);
+            cc[dz][dy] = v0 * (1.0 - w[0]) + v1 * w[0];
         }
-    double e0 = c[0][0] * (1.0 - w[1]) + c[0][1] * w[1];
-    double e1 = c[1][0] * (1.0 - w[1]) + c[1][1] * w[1];
+    double e0 = cc[0][0] * (1.0 - w[1]) + cc[0][1] * w[1];
+    double e1 = cc[1][0] * (1.0 - w[1]) + cc[1][1] * w[1];
     return e0 * (1.0 - w[2]) + e1 * w[2];
+}
+
+static tile_t *new_tiles(void) {
+    tile_t *t = (tile_t *)malloc(sizeof(tile_t) * TCACHE);
+    if (t)
+        for (int i = 0; i < TCACHE; ++i) t[i].key[0] = -1;
+    return t;
 }
 
 /* Ray of pixel (i, j), row 0 at the top: a = (2i+1-W)/W, b = (H-2j-1)/H.
@@ -462,10 +528,11 @@ typedef struct {
  *   amb_used[slot]     slots read by samples after an ambiguous termination
  * Every pixel's ray samples t_k = k delta, k = 0, 1, ...; samples outside
  * [0, dims) are void.  Early termination when A >= term_alpha. */
-int or_render(const or_volume *V, const void *const *lvl, const int32_t *res_slot,
-              const uint16_t *leaf_mm, const or_frame *Fr, double *rgba, uint32_t *counts,
-              uint8_t *used, uint32_t *aov, uint8_t *amb_pix, uint32_t *amb_counts,
-              uint8_t *amb_used, or_stats *stats, int n_threads) {
+int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, const or_source *src,
+              const int32_t *res_slot, const uint16_t *leaf_mm, const or_frame *Fr, int row0,
+              int row1, double *rgba, uint32_t *counts, uint8_t *used, uint32_t *aov,
+              uint8_t *amb_pix, uint32_t *amb_counts, uint8_t *amb_used, or_stats *stats,
+              int n_threads) {
     geo_t G;
     tree_t T;
     geo(V, &G);
@@ -482,11 +549,18 @@ int or_render(const or_volume *V, const void *const *lvl, const int32_t *res_slo
         if (Fr->proj == 0 && Fr->lod_bias * pix >= s_l) n_ortho++;
     }
     long long st_s = 0, st_cs = 0, st_m = 0, st_as = 0, st_ap = 0;
+    if (!lvl && !(src && src->fetch)) return -1;
+    if (row0 < 0) row0 = 0;
+    if (row1 <= 0 || row1 > Fr->H) row1 = Fr->H;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #endif
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : st_s, st_cs, st_m, st_as, st_ap)
-    for (int j = 0; j < Fr->H; ++j) {
+#pragma omp parallel reduction(+ : st_s, st_cs, st_m, st_as, st_ap)
+    {
+    sampler_t SM = {V, lvl, lvl_box, src, lvl ? NULL : new_tiles(), (const int(*)[3])G.dl,
+                    (const int(*)[3])G.f, L};
+#pragma omp for schedule(dynamic, 1)
+    for (int j = row0; j < row1; ++j) {
         for (int i = 0; i < Fr->W; ++i) {
             long long pidx = (long long)j * Fr->W + i;
             double o[3], d[3], t0, t1;
@@ -576,7 +650,7 @@ int or_render(const or_volume *V, const void *const *lvl, const int32_t *res_slo
                         }
                         double q[3];
                         for (int a = 0; a < 3; ++a) q[a] = u[a] / G.f[lu][a];
-                        double v = trilinear(V, lvl[c * L + lu], G.dl[lu], q);
+                        double v = trilinear(&SM, c, lu, q);
                         double rgbaC[4];
                         tf_eval(v, Fr->W0[jv], Fr->W1[jv], Fr->tf[jv], rgbaC);
                         double ac = rgbaC[3];
@@ -614,6 +688,8 @@ int or_render(const or_volume *V, const void *const *lvl, const int32_t *res_slo
             if (pamb) st_ap++;
         }
     }
+    free(SM.tiles);
+    }
     if (stats) {
         stats->samples = st_s;
         stats->channel_samples = st_cs;
@@ -631,7 +707,8 @@ int or_brute(const or_volume *V, const void *const *lvl, int lambda, const or_fr
              double *rgba) {
     geo_t G;
     geo(V, &G);
-    if (lambda < 0 || lambda >= G.L) return -1;
+    if (lambda < 0 || lambda >= G.L || !lvl) return -1;
+    sampler_t SM = {V, lvl, NULL, NULL, NULL, (const int(*)[3])G.dl, (const int(*)[3])G.f, G.L};
 #pragma omp parallel for schedule(dynamic, 1)
     for (int j = 0; j < Fr->H; ++j)
         for (int i = 0; i < Fr->W; ++i) {
@@ -654,7 +731,7 @@ int or_brute(const or_volume *V, const void *const *lvl, int lambda, const or_fr
                         int c = Fr->vis[jv];
                         double q[3];
                         for (int a = 0; a < 3; ++a) q[a] = u[a] / G.f[lambda][a];
-                        double v = trilinear(V, lvl[c * G.L + lambda], G.dl[lambda], q);
+                        double v = trilinear(&SM, c, lambda, q);
                         double r[4];
                         tf_eval(v, Fr->W0[jv], Fr->W1[jv], Fr->tf[jv], r);
                         prod *= (1.0 - r[3]);

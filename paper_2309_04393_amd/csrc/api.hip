@@ -267,6 +267,57 @@ extern "C" ro_status ro_cache_page_table_host(const ro_cache *c, uint32_t *out, 
     return RO_OK;
 }
 
+// Checkpoint blob: header, then the page-table mirror, slot mirror and dirty list.
+struct StateHeader {
+    uint64_t magic, total, slots, dirty;
+    uint32_t seq_next, pad;
+};
+static const uint64_t kStateMagic = 0x31455441545352ull;  // "RSTATE1"
+
+extern "C" ro_status ro_cache_state_size(const ro_cache *c, size_t *bytes) {
+    RO_CHECK(c && bytes, RO_E_ARG, "null argument");
+    *bytes = sizeof(StateHeader) + 4 * (c->pt_host.size() + c->slot_host.size() + c->dirty.size());
+    return RO_OK;
+}
+
+extern "C" ro_status ro_cache_save_state(const ro_cache *c, void *host, size_t cap) {
+    size_t need = 0;
+    ro_status st = ro_cache_state_size(c, &need);
+    if (st) return st;
+    RO_CHECK(host && cap >= need, RO_E_ARG, "buffer of %zu bytes needed", need);
+    StateHeader hd = {kStateMagic, c->pt_host.size(), c->slot_host.size(), c->dirty.size(), c->seq_next, 0};
+    uint8_t *p = (uint8_t *)host;
+    memcpy(p, &hd, sizeof(hd));
+    p += sizeof(hd);
+    memcpy(p, c->pt_host.data(), 4 * c->pt_host.size());
+    p += 4 * c->pt_host.size();
+    memcpy(p, c->slot_host.data(), 4 * c->slot_host.size());
+    p += 4 * c->slot_host.size();
+    if (!c->dirty.empty()) memcpy(p, c->dirty.data(), 4 * c->dirty.size());
+    return RO_OK;
+}
+
+extern "C" ro_status ro_cache_load_state(ro_cache *c, const void *host, size_t size) {
+    RO_CHECK(c && host && size >= sizeof(StateHeader), RO_E_ARG, "bad state blob");
+    StateHeader hd;
+    memcpy(&hd, host, sizeof(hd));
+    RO_CHECK(hd.magic == kStateMagic && hd.total == c->pt_host.size() && hd.slots == c->slot_host.size() &&
+                 size == sizeof(hd) + 4 * (hd.total + hd.slots + hd.dirty),
+             RO_E_ARG, "state blob does not match this cache");
+    const uint8_t *p = (const uint8_t *)host + sizeof(hd);
+    try {
+        std::vector<uint32_t> dirty(hd.dirty);
+        if (hd.dirty) memcpy(dirty.data(), p + 4 * (hd.total + hd.slots), 4 * hd.dirty);
+        c->dirty.swap(dirty);
+    } catch (...) {
+        RO_CHECK(false, RO_E_NOMEM, "out of host memory");
+    }
+    memcpy(c->pt_host.data(), p, 4 * hd.total);
+    memcpy(c->slot_host.data(), p + 4 * hd.total, 4 * hd.slots);
+    c->seq_next = hd.seq_next;
+    return RO_OK;
+}
+
 extern "C" ro_status ro_stream_bricks(ro_cache *c, uint32_t frame, uint32_t n,
                                       const uint32_t *ids, const void *staged, uint8_t *flags,
                                       void *stream) {

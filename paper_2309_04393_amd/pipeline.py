@@ -56,16 +56,31 @@ class GpuScene:
         n = len(ids)
         stride = self.cache.slot_stride
         host = np.zeros((max(n, 1), stride), np.uint8)
-        groups = {}
-        for i, id_ in enumerate(ids):
-            c, l, b = self.vol.decode(int(id_))
-            groups.setdefault((c, l), []).append((i, b))
         nbytes = self.E ** 3 * (1 if self.np_dtype == np.uint8 else 2)
-        for (c, l), lst in groups.items():
-            br = self.src.bricks(c, l, [b for _, b in lst], self.B)
-            raw = np.ascontiguousarray(br).view(np.uint8).reshape(len(lst), nbytes)
-            for k, (i, _) in enumerate(lst):
-                host[i, :nbytes] = raw[k]
+        dec = [self.vol.decode(int(i)) for i in ids]
+        if hasattr(self.src, "bricks_multi"):
+            # one generator pass per brick position serves every channel there
+            groups = {}
+            for i, (c, l, b) in enumerate(dec):
+                groups.setdefault(l, {}).setdefault(b, []).append((i, c))
+            for l, pos in groups.items():
+                coords = list(pos.keys())
+                chs = sorted({c for lst in pos.values() for _, c in lst})
+                cidx = {c: k for k, c in enumerate(chs)}
+                br = self.src.bricks_multi(l, coords, self.B, chs)
+                raw = np.ascontiguousarray(br).view(np.uint8).reshape(len(coords), len(chs), nbytes)
+                for p_i, b in enumerate(coords):
+                    for (i, c) in pos[b]:
+                        host[i, :nbytes] = raw[p_i, cidx[c]]
+        else:
+            groups = {}
+            for i, (c, l, b) in enumerate(dec):
+                groups.setdefault((c, l), []).append((i, b))
+            for (c, l), lst in groups.items():
+                br = self.src.bricks(c, l, [b for _, b in lst], self.B)
+                raw = np.ascontiguousarray(br).view(np.uint8).reshape(len(lst), nbytes)
+                for k, (i, _) in enumerate(lst):
+                    host[i, :nbytes] = raw[k]
         return torch.from_numpy(host.reshape(-1)).to(self.device)
 
     def upload(self, frame: int, ids, staged: torch.Tensor = None) -> np.ndarray:

@@ -71,7 +71,7 @@ class FrameDesc(ctypes.Structure):
                 ("n_vis", c_i32), ("vis", c_i32 * MAX_CHANNELS), ("lod_lo", c_i32 * MAX_CHANNELS),
                 ("lod_hi", c_i32 * MAX_CHANNELS), ("win_lo", c_u32 * MAX_CHANNELS),
                 ("win_hi", c_u32 * MAX_CHANNELS), ("tf_dev", c_vp), ("term_alpha", ctypes.c_float),
-                ("start_level", c_i32), ("flags", c_u32), ("aov_dev", c_vp)]
+                ("start_level", c_i32), ("flags", c_u32), ("aov_dev", c_vp), ("stats_dev", c_vp)]
 
 
 def _sig(name, res, args):
@@ -96,6 +96,9 @@ _sig("ro_stream_bricks", c_i32, [c_vp, c_u32, c_u32, c_vp, c_vp, c_vp, c_vp])
 _sig("ro_read_requests", c_i32, [c_vp, c_u32, c_vp, c_vp, _P(c_u32), _P(c_u64), c_vp])
 _sig("ro_read_usage", c_i32, [c_vp, c_u32, c_u32, c_vp, _P(c_u32), c_vp])
 _sig("ro_cache_page_table_host", c_i32, [c_vp, c_vp, c_u64])
+_sig("ro_cache_state_size", c_i32, [c_vp, _P(c_sz)])
+_sig("ro_cache_save_state", c_i32, [c_vp, c_vp, c_sz])
+_sig("ro_cache_load_state", c_i32, [c_vp, c_vp, c_sz])
 _sig("ro_octree_query", c_i32, [c_vp, _P(OctreeDesc), _P(OctreeSizes)])
 _sig("ro_octree_create", c_i32, [c_vp, _P(OctreeDesc), _P(OctreeBuffers), c_vp, _P(c_vp)])
 _sig("ro_octree_destroy", None, [c_vp])
@@ -242,6 +245,17 @@ class Cache:
                "ro_read_usage")
         return out[:min(cap, n.value)], int(n.value)
 
+    def save_state(self) -> np.ndarray:
+        n = c_sz()
+        _check(_lib.ro_cache_state_size(self.h, ctypes.byref(n)), "ro_cache_state_size")
+        blob = np.zeros(n.value, np.uint8)
+        _check(_lib.ro_cache_save_state(self.h, _np_ptr(blob), n.value), "ro_cache_save_state")
+        return blob
+
+    def load_state(self, blob: np.ndarray):
+        blob = np.ascontiguousarray(blob, dtype=np.uint8)
+        _check(_lib.ro_cache_load_state(self.h, _np_ptr(blob), blob.size), "ro_cache_load_state")
+
     def page_table_host(self) -> np.ndarray:
         out = np.zeros(self.n_bricks, np.uint32)
         _check(_lib.ro_cache_page_table_host(self.h, _np_ptr(out), self.n_bricks),
@@ -305,7 +319,7 @@ class Octree:
 
 def frame_desc(frame: int, cam: dict, W: int, H: int, step: float, channels: list, tf_dev: torch.Tensor,
                n_levels: int, term_alpha=0.99, lod_bias=1.0, start_level=-1, flags=0,
-               aov: torch.Tensor = None):
+               aov: torch.Tensor = None, stats: torch.Tensor = None):
     """channels: list of {c, lo, hi, W0, W1} in visible-slot order (lo / hi
     default to the full level range); tf_dev is a device float32 tensor
     [n_vis][256][4] in the same order."""
@@ -332,4 +346,5 @@ def frame_desc(frame: int, cam: dict, W: int, H: int, step: float, channels: lis
     fd.start_level = start_level
     fd.flags = flags | (RENDER_AOV if aov is not None else 0)
     fd.aov_dev = aov.data_ptr() if aov is not None else None
+    fd.stats_dev = stats.data_ptr() if stats is not None else None
     return fd

@@ -61,7 +61,7 @@ class Pair:
         m_or = oracle.masks(self.V, self.sim.res_slot)
         assert np.array_equal(m_gpu, m_or), f"masks differ at {np.argwhere(m_gpu != m_or)[:5]}"
 
-    def frame(self, f, cam, W, H, step, chans, term_margin=1e-5, aov=False, **kw):
+    def frame(self, f, cam, W, H, step, chans, term_margin=2e-6, aov=False, **kw):
         r = self.gpu.render(f, cam, W, H, step, chans, aov=aov, **kw)
         torch.cuda.synchronize()
         ids, cnt, nu, tot = self.gpu.cache.read_requests(1 << 20)
