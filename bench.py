@@ -95,7 +95,7 @@ class Frames:
         self.W, self.H, self.U, self.step = W, H, U, step
         self.tf = scene.tf_tensor(chans)
         self.out = torch.empty(W * H * 4, dtype=torch.float32, device="cuda")
-        self.stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+        self.stats = torch.zeros(8, dtype=torch.int64, device="cuda")
 
     def render(self, f, cam_index=None):
         return self.s.render(f, self.cams[f if cam_index is None else cam_index], self.W, self.H,
@@ -263,6 +263,9 @@ def main():
     ap.add_argument("--config", default="cfg3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=192)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the measurement, copy a 1 GiB buffer three times (a plain copy kernel of "
+                         "known size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -374,6 +377,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_render", "alg_bytes_per_launch": float(np.mean(alg_bytes))},
     }
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 1 << 30
     if not args.no_cpu_baseline:
         try:
             cb, _ = cpu_baseline(cfg, scene, cams, chans, f0, step, args.tile)

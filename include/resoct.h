@@ -286,14 +286,78 @@ typedef struct {
     int32_t start_level;  /* traversal start level (Sec. 6, implementation), -1: the octree's */
     uint32_t flags;       /* RO_RENDER_* */
     uint32_t *aov_dev;    /* RO_RENDER_AOV: device [H][W][k] uint32, zeroed by the caller */
-    unsigned long long *stats_dev; /* optional device [4], accumulated (not cleared): ray samples
-                                      evaluated, channel samples read from bricks, channel samples
-                                      whose desired brick was missing, leaf visits */
+    unsigned long long *stats_dev; /* optional device [8], accumulated (not cleared): [0] ray
+                                      samples evaluated, [1] channel samples read from bricks,
+                                      [2] channel samples whose desired brick was missing,
+                                      [3] (leaf, level) visits, [4] channel samples in leaves
+                                      that are not empty for the channel; [5..7] zero */
 } ro_frame_desc;
 
 /* Renders into rgba_dev[H][W][4] (float, premultiplied) and updates the
  * miss counters and slot stamps.  Asynchronous. */
 ro_status ro_render(ro_octree *t, const ro_frame_desc *fd, float *rgba_dev, void *stream);
+
+/* ------------------------------------------------------------- predictor */
+
+/* Brick-request predictor: an addition to the paper's method that only
+ * changes which bricks a policy streams, never the image rendered from a
+ * given cache state.  A perceptron 24 -> 64 -> 64 -> 9 with ReLU hidden
+ * layers and one logit per resolution level:
+ *   h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), z = h2 W3 + b3,
+ * trained with binary cross-entropy on the logits, masked per (row, level),
+ * mean over unmasked entries, by Adam (beta 0.9 / 0.999, eps 1e-8) on FP32
+ * master weights.  Products run on MFMA with FP16 operands and FP32
+ * accumulation.  Device layouts: features x [rows][32] FP16 (features
+ * 0..23, the rest zero); logits z [rows][16] FP32 (0..8 used); labels y and
+ * mask [rows][16] uint8 0/1.  Host weight layout (FP32, input-major):
+ * W1[24][64], b1[64], W2[64][64], b2[64], W3[64][9], b3[9] (6217 floats). */
+typedef struct ro_mlp ro_mlp;
+ro_status ro_mlp_query(size_t *param_bytes, size_t *workspace_bytes);
+ro_status ro_mlp_create(void *params_dev, void *workspace_dev, ro_mlp **out);
+void ro_mlp_destroy(ro_mlp *n);
+/* Loads weights and resets the optimiser state.  Synchronises. */
+ro_status ro_mlp_set_weights(ro_mlp *n, const float *host, void *stream);
+ro_status ro_mlp_get_weights(const ro_mlp *n, float *host, void *stream); /* synchronises */
+ro_status ro_mlp_forward(ro_mlp *n, const uint16_t *x_dev, uint32_t rows, float *z_dev, void *stream);
+/* Gradient of the loss at the current weights (host layout above) and the
+ * loss; no update.  Synchronises. */
+ro_status ro_mlp_gradients(ro_mlp *n, const uint16_t *x_dev, const uint8_t *y_dev, const uint8_t *mask_dev,
+                           uint32_t rows, float *grads_host, float *loss_host, void *stream);
+/* One Adam step; *loss_host (if not NULL) receives the loss before the step
+ * (then the call synchronises). */
+ro_status ro_mlp_train_step(ro_mlp *n, const uint16_t *x_dev, const uint8_t *y_dev, const uint8_t *mask_dev,
+                            uint32_t rows, float lr, float *loss_host, void *stream);
+
+/* Predictor rows and bookkeeping.  Rows: one per (cache channel c, L0 brick
+ * position p), row = c * P + p, p = (z * nby + y) * nbx + x over the L0
+ * brick grid (P positions, m * P rows).  History: one byte per brick, bits
+ * 0-3 requested in the last four frames (bit 0 = latest), bits 4-7 read in
+ * them.  Features (24 per row, FP16, written into x_dev[rows][32]): brick
+ * edge in pixels and distance relative to the first level threshold (log2),
+ * desired level, frustum flag, projected position, depth, fraction of the
+ * brick's leaves not empty under the channel's transfer function (0 when the
+ * channel is not visible), request and read history of the L0 brick,
+ * residency of the bricks covering it at levels 0..7.  Labels: level l of a
+ * row is 1 iff the level-l brick covering the row's position was requested
+ * or read in the last four frames (use with features from four frames
+ * before); mask = 1 for existing levels (at most 9). */
+typedef struct ro_prefetch ro_prefetch;
+ro_status ro_pf_query(const ro_octree *t, uint32_t *rows, size_t *hist_bytes, size_t *score_bytes);
+/* hist_dev and score_dev are caller-allocated device buffers of the queried
+ * sizes; both are cleared. */
+ro_status ro_pf_create(ro_octree *t, uint8_t *hist_dev, uint32_t *score_dev, void *stream, ro_prefetch **out);
+void ro_pf_destroy(ro_prefetch *p);
+/* Shift the history and record this frame's requests (miss counters, so call
+ * after ro_render and before ro_read_requests) and reads (stamp == frame). */
+ro_status ro_pf_record(ro_prefetch *p, uint32_t frame, void *stream);
+ro_status ro_pf_features(ro_prefetch *p, const ro_frame_desc *fd, uint16_t *x_dev, void *stream);
+ro_status ro_pf_labels(ro_prefetch *p, uint8_t *y_dev, uint8_t *mask_dev, void *stream);
+/* Bricks not resident whose predicted probability sigmoid(z) exceeds
+ * `threshold` for some row (z_dev [rows][16] logits), with the best
+ * probability per brick, in ascending ID order; at most cap returned,
+ * *n_out = all of them.  Synchronises. */
+ro_status ro_pf_candidates(ro_prefetch *p, const float *z_dev, float threshold, uint32_t cap, uint32_t *ids_host,
+                           float *prob_host, uint32_t *n_out, void *stream);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char *ro_last_error(void);

@@ -238,6 +238,9 @@ def render(V: Volume, levels, res_slot, leaf_mm, frame: Frame, n_slots: int, aov
     of the level (samples outside it read NaN)."""
     W, H = frame.W, frame.H
     nb = brick_count(V)
+    rs = np.ascontiguousarray(res_slot, dtype=np.int32)
+    # the usage arrays are indexed by slot: cover every slot the resident set names
+    n_slots = max(int(n_slots), int(rs.max()) + 1 if rs.size else 0)
     rgba = np.zeros((H, W, 4), np.float64)
     counts = np.zeros(nb, np.uint32)
     used = np.zeros(max(n_slots, 1), np.uint8)
@@ -249,7 +252,6 @@ def render(V: Volume, levels, res_slot, leaf_mm, frame: Frame, n_slots: int, aov
         ptrs, keep = _level_ptrs(V, levels)
     else:
         ptrs, keep = None, None
-    rs = np.ascontiguousarray(res_slot, dtype=np.int32)
     lm = np.ascontiguousarray(leaf_mm, dtype=np.uint16)
     st = Stats()
     r0, r1 = rows if rows is not None else (0, 0)

@@ -1,0 +1,424 @@
+// Per-ray core of the residency-octree ray caster, shared by the frame kernel
+// (render.hip) and the multi-request serving kernel (serve.hip).
+#pragma once
+
+#include <math.h>
+
+#include "common.h"
+
+namespace ro {
+
+struct RenderArgs {
+    // scalars
+    int32_t dims[3];
+    double sp[3];
+    int32_t m, L, Blog, E, depth, start_level;
+    uint32_t per_channel, slot_stride;
+    double eye[3], F[3], R[3], U[3];
+    double tx, ty, step;
+    int32_t proj, W, H;
+    int32_t nvis;
+    float term;
+    uint32_t frame, flags;
+    // uniform tables copied to LDS by the workgroup
+    int32_t vis[kMaxC], lo[kMaxC], hi[kMaxC];
+    uint32_t W0[kMaxC], W1[kMaxC];
+    float w0[kMaxC], iw[kMaxC];
+    uint32_t lsh[kMaxL];   // per level: packed log2 factors x | y << 8 | z << 16
+    uint32_t loff[kMaxL];  // brick offset of the level inside a channel
+    uint32_t nbx[kMaxL], nby[kMaxL];
+    uint32_t K[kMaxL];     // level l is desired from sample index K[l] on
+    uint32_t nsh[kMaxD + 1];   // per tree level: packed log2 node edge
+    uint32_t nlg[kMaxD + 1];   // per tree level: packed log2 node count
+    uint32_t noff[kMaxD + 1];  // node offset of the level
+    // device buffers
+    const uint8_t *slots;
+    const uint32_t *pt;
+    uint32_t *cnt;
+    uint32_t *stamp;
+    const uint32_t *meta;
+    const uint16_t *mask;
+    const float4 *tf;
+    float *rgba;
+    uint32_t *aov;
+    unsigned long long *stats;
+};
+
+struct ChanLds {
+    int c, lo, hi, nruns;
+    float w0, iw;
+};
+
+struct LevLds {
+    uint32_t sh;   // packed shifts (level factor + brick) per axis
+    uint32_t raw;  // packed level factor shifts
+    uint32_t loff, nbx, nbxy, K;
+};
+
+struct NodeLds {
+    uint32_t nsh, nlg, noff;
+};
+
+__device__ __forceinline__ uint32_t field(uint32_t p, int a) { return (p >> (8 * a)) & 255u; }
+
+// Zero-alpha runs of a channel's table as raw-value bounds (lo | hi << 16):
+// the range [mn, mx] is empty iff some run has mn >= lo and mx <= hi.  Raw
+// values are at most 65535, so runs whose lower bound exceeds that are
+// dropped and upper bounds are clamped to 65535.  Bounds from the window
+// (24.8 fixed point, den = W1 - W0):
+// floor(255 (256 r - W0) / den) >= a  <=>  r >= ceil((255 W0 + a den) / 65280)
+// ceil (255 (256 r - W0) / den) <= b  <=>  r <= floor((255 W0 + b den) / 65280)
+__device__ inline int build_runs(const float4 *tf, uint32_t W0, uint32_t W1, uint32_t *runs) {
+    int n = 0, e = 0;
+    const uint64_t den = (uint64_t)W1 - (uint64_t)W0;
+    while (e < 256) {
+        if (tf[e].w != 0.0f) {
+            ++e;
+            continue;
+        }
+        const int a = e;
+        while (e < 256 && tf[e].w == 0.0f) ++e;
+        const int b = e - 1;
+        uint64_t rlo = a == 0 ? 0 : (255ull * W0 + (uint64_t)a * den + 65279ull) / 65280ull;
+        uint64_t rhi = b == 255 ? 65535ull : (255ull * W0 + (uint64_t)b * den) / 65280ull;
+        if (rhi > 65535ull) rhi = 65535ull;
+        if (rlo <= rhi && n < kMaxRuns) runs[n++] = (uint32_t)rlo | ((uint32_t)rhi << 16);
+    }
+    return n;
+}
+
+__device__ __forceinline__ bool range_empty(uint32_t mm, const uint32_t *runs, int nr) {
+    const uint32_t mn = mm & 0xFFFFu, mx = mm >> 16;
+    for (int r = 0; r < nr; ++r) {
+        const uint32_t q = runs[r];
+        if (mn >= (q & 0xFFFFu) && mx <= (q >> 16)) return true;
+    }
+    return false;
+}
+
+template <int BPV>
+__device__ __forceinline__ float voxel(const uint8_t *p, uint32_t idx) {
+    if (BPV == 1) return (float)p[idx];
+    return (float)((const uint16_t *)p)[idx];
+}
+
+__device__ __forceinline__ uint32_t brick_dense(const LevLds &lv, uint32_t c, uint32_t per_channel, int bx,
+                                                int by, int bz) {
+    return c * per_channel + lv.loff + (uint32_t)bz * lv.nbxy + (uint32_t)by * lv.nbx + (uint32_t)bx;
+}
+
+__device__ __forceinline__ uint32_t node_at(const NodeLds &nd, int x, int y, int z) {
+    return nd.noff + ((((uint32_t)z << field(nd.nlg, 1)) + (uint32_t)y) << field(nd.nlg, 0)) + (uint32_t)x;
+}
+
+template <int NV, int BPV, bool AOV>
+__device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, const int py, const float4 *s_tf,
+                                             const ChanLds *s_ch, const uint32_t *s_runs, const LevLds *s_lv,
+                                             const NodeLds *s_nd, uint32_t stats[5]) {
+    const int nvis = A.nvis;
+    const int D = A.depth;
+    const int L = A.L;
+    const int m = A.m;
+
+    // ---- ray in L0 voxel units
+    double o[3], d[3];
+    {
+        const double a = (double)(2 * px + 1 - A.W) / (double)A.W;
+        const double b = (double)(A.H - 2 * py - 1) / (double)A.H;
+        double ow[3], dw[3];
+        if (A.proj == RO_PROJ_ORTHO) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                ow[k] = A.eye[k] + a * A.tx * A.R[k] + b * A.ty * A.U[k];
+                dw[k] = A.F[k];
+            }
+        } else {
+            double n = 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                ow[k] = A.eye[k];
+                dw[k] = A.F[k] + a * A.tx * A.R[k] + b * A.ty * A.U[k];
+                n += dw[k] * dw[k];
+            }
+            n = sqrt(n);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) dw[k] = dw[k] / n;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            o[k] = ow[k] / A.sp[k];
+            d[k] = dw[k] / A.sp[k];
+        }
+    }
+    double Cr = 0, Cg = 0, Cb = 0, Tr = 1.0;
+    const double one_minus_term = 1.0 - (double)A.term;
+    float *out = A.rgba + ((size_t)py * A.W + px) * 4;
+
+    // ---- box interval
+    double t0 = -INFINITY, t1 = INFINITY;
+    bool hit = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (d[k] == 0.0) {
+            if (o[k] < 0.0 || o[k] >= (double)A.dims[k]) hit = false;
+            continue;
+        }
+        double u = (0.0 - o[k]) / d[k], v = ((double)A.dims[k] - o[k]) / d[k];
+        if (u > v) {
+            const double s = u;
+            u = v;
+            v = s;
+        }
+        t0 = fmax(t0, u);
+        t1 = fmin(t1, v);
+    }
+    if (!hit || t0 > t1) {
+        out[0] = out[1] = out[2] = out[3] = 0.0f;
+        return;
+    }
+    long long k = (long long)floor(t0 / A.step) - 1;
+    if (k < 0) k = 0;
+    const long long kend = (long long)ceil(t1 / A.step) + 1;
+
+    // ---- visit state
+    uint32_t cur_leaf = kInvalid;
+    int cur_lod = -1, lod = 0;
+    while (lod + 1 < L && (unsigned long long)k >= s_lv[lod + 1].K) ++lod;
+    uint32_t emask = 0, missmask = 0;
+    uint32_t slot[NV];
+    uint64_t lvpack = 0;
+    uint32_t nvisit = 0;
+    uint32_t st_samples = 0, st_reads = 0, st_miss = 0, st_visits = 0, st_nonempty = 0;
+    const uint32_t vismask = (nvis >= 32) ? 0xFFFFFFFFu : ((1u << nvis) - 1u);
+    int lc[3] = {0, 0, 0};  // L0 origin of the visit's leaf
+#pragma unroll
+    for (int j = 0; j < NV; ++j) slot[j] = kInvalid;
+    const int s0 = A.start_level;
+    const bool noskip = (A.flags & RO_RENDER_NO_SKIP) != 0;
+    const NodeLds leafl = s_nd[D];
+
+    auto flush = [&]() {
+        if (missmask && nvisit) {
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                if (j < nvis && ((missmask >> j) & 1u)) {
+                    const ChanLds ch = s_ch[j];
+                    const int ls = min(max(cur_lod, ch.lo), ch.hi);
+                    const LevLds lv = s_lv[ls];
+                    const int bx = lc[0] >> field(lv.sh, 0), by = lc[1] >> field(lv.sh, 1),
+                              bz = lc[2] >> field(lv.sh, 2);
+                    atomicAdd(&A.cnt[brick_dense(lv, (uint32_t)ch.c, A.per_channel, bx, by, bz)], nvisit);
+                    st_miss += nvisit;
+                }
+            }
+        }
+        nvisit = 0;
+    };
+
+    while (k <= kend) {
+        const double t = (double)k * A.step;
+        double u[3];
+        bool inside = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            u[a] = o[a] + t * d[a];
+            inside = inside && (u[a] >= 0.0) && (u[a] < (double)A.dims[a]);
+        }
+        if (!inside) {
+            ++k;
+            continue;
+        }
+        const int iu[3] = {(int)u[0], (int)u[1], (int)u[2]};
+        while (lod + 1 < L && (unsigned long long)k >= s_lv[lod + 1].K) ++lod;
+        const uint32_t leaf = node_at(leafl, iu[0] >> field(leafl.nsh, 0), iu[1] >> field(leafl.nsh, 1),
+                                      iu[2] >> field(leafl.nsh, 2));
+        if (leaf != cur_leaf || lod != cur_lod) {
+            flush();
+            if (leaf != cur_leaf) {
+                // descend from the start level; skip the first node that is
+                // empty for every visible channel (the leaf included)
+                bool skipped = false;
+                for (int dl = noskip ? D : s0; dl <= D; ++dl) {
+                    const NodeLds nd = s_nd[dl];
+                    const uint32_t node = node_at(nd, iu[0] >> field(nd.nsh, 0), iu[1] >> field(nd.nsh, 1),
+                                                  iu[2] >> field(nd.nsh, 2));
+                    uint32_t em = 0;
+                    for (int j = 0; j < nvis; ++j) {
+                        const ChanLds ch = s_ch[j];
+                        if (range_empty(A.meta[(size_t)node * m + ch.c], s_runs + j * kMaxRuns, ch.nruns))
+                            em |= 1u << j;
+                    }
+                    if (dl == D) emask = em;
+                    if (em == (1u << nvis) - 1u && !noskip) {
+                        double te = INFINITY;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            if (d[a] == 0.0) continue;
+                            const int sh = (int)field(nd.nsh, a);
+                            const double lo_a = (double)((iu[a] >> sh) << sh);
+                            const double bound = d[a] > 0.0 ? lo_a + (double)(1 << sh) : lo_a;
+                            te = fmin(te, (bound - o[a]) / d[a]);
+                        }
+                        const long long kn = (long long)floor(te / A.step) - 1;
+                        k = kn > k + 1 ? kn : k + 1;
+                        skipped = true;
+                        break;
+                    }
+                }
+                if (skipped) {
+                    cur_leaf = kInvalid;
+                    continue;
+                }
+                cur_leaf = leaf;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) lc[a] = (iu[a] >> field(leafl.nsh, a)) << field(leafl.nsh, a);
+            }
+            cur_lod = lod;
+            ++st_visits;
+            missmask = 0;
+            lvpack = 0;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                uint32_t ns = kInvalid;
+                if (j < nvis && !((emask >> j) & 1u)) {
+                    const ChanLds ch = s_ch[j];
+                    const int ls = min(max(lod, ch.lo), ch.hi);
+                    const uint32_t mk = (uint32_t)A.mask[(size_t)leaf * m + ch.c] >> ls;
+                    if (!(mk & 1u)) missmask |= 1u << j;
+                    if (mk) {
+                        const int lu = ls + __builtin_ctz(mk);
+                        const LevLds lv = s_lv[lu];
+                        ns = A.pt[brick_dense(lv, (uint32_t)ch.c, A.per_channel, iu[0] >> field(lv.sh, 0),
+                                              iu[1] >> field(lv.sh, 1), iu[2] >> field(lv.sh, 2))];
+                        if (ns != kInvalid) {
+                            lvpack |= (uint64_t)lu << (4 * j);
+                            if (ns != slot[j]) A.stamp[ns] = A.frame;
+                        }
+                    }
+                }
+                slot[j] = ns;
+            }
+        }
+        ++nvisit;
+        ++st_samples;
+        st_nonempty += __popc(vismask & ~emask);
+        // ---- sample every visible channel
+        float prod = 1.0f, sa = 0.0f, sr = 0.0f, sg = 0.0f, sbl = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            if (j < nvis && slot[j] != kInvalid) {
+                const int lu = (int)((lvpack >> (4 * j)) & 15u);
+                const LevLds lv = s_lv[lu];
+                int i0[3];
+                float fr[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int s = (int)field(lv.raw, a);
+                    const double ul = ldexp(u[a], -s);
+                    const int b = (iu[a] >> field(lv.sh, a)) << A.Blog;
+                    const double q = ul + 0.5 - (double)b;
+                    i0[a] = (int)q;
+                    fr[a] = (float)(q - (double)i0[a]);
+                }
+                const uint8_t *base = A.slots + (size_t)slot[j] * A.slot_stride;
+                const uint32_t E = (uint32_t)A.E;
+                const uint32_t idx = ((uint32_t)i0[2] * E + (uint32_t)i0[1]) * E + (uint32_t)i0[0];
+                const float v000 = voxel<BPV>(base, idx), v100 = voxel<BPV>(base, idx + 1);
+                const float v010 = voxel<BPV>(base, idx + E), v110 = voxel<BPV>(base, idx + E + 1);
+                const float v001 = voxel<BPV>(base, idx + E * E), v101 = voxel<BPV>(base, idx + E * E + 1);
+                const float v011 = voxel<BPV>(base, idx + E * E + E), v111 = voxel<BPV>(base, idx + E * E + E + 1);
+                const float c00 = v000 + (v100 - v000) * fr[0];
+                const float c10 = v010 + (v110 - v010) * fr[0];
+                const float c01 = v001 + (v101 - v001) * fr[0];
+                const float c11 = v011 + (v111 - v011) * fr[0];
+                const float e0 = c00 + (c10 - c00) * fr[1];
+                const float e1 = c01 + (c11 - c01) * fr[1];
+                const float v = e0 + (e1 - e0) * fr[2];
+                const ChanLds ch = s_ch[j];
+                float x = (v - ch.w0) * ch.iw;
+                x = fminf(fmaxf(x, 0.0f), 1.0f);
+                const float p = x * 255.0f;
+                int e = (int)p;
+                e = e > 255 ? 255 : e;
+                const int e1i = e < 255 ? e + 1 : 255;
+                const float f = p - (float)e;
+                const float4 ta = s_tf[j * 256 + e], tb = s_tf[j * 256 + e1i];
+                const float al = ta.w + (tb.w - ta.w) * f;
+                const float r = ta.x + (tb.x - ta.x) * f;
+                const float gg = ta.y + (tb.y - ta.y) * f;
+                const float bb = ta.z + (tb.z - ta.z) * f;
+                ++st_reads;
+                prod *= 1.0f - al;
+                sa += al;
+                sr += al * r;
+                sg += al * gg;
+                sbl += al * bb;
+                if (AOV) A.aov[((size_t)py * A.W + px) * L + lu] += 1;
+            }
+        }
+        if (sa > 0.0f) {
+            const float as = 1.0f - prod;
+            const float sc = as / sa;
+            Cr += Tr * (double)(sr * sc);
+            Cg += Tr * (double)(sg * sc);
+            Cb += Tr * (double)(sbl * sc);
+            Tr *= 1.0 - (double)as;
+            if (Tr <= one_minus_term) break;
+        }
+        ++k;
+    }
+    flush();
+    out[0] = (float)Cr;
+    out[1] = (float)Cg;
+    out[2] = (float)Cb;
+    out[3] = (float)(1.0 - Tr);
+    stats[0] = st_samples;
+    stats[1] = st_reads;
+    stats[2] = st_miss;
+    stats[3] = st_visits;
+    stats[4] = st_nonempty;
+}
+
+// Workgroup set-up: stage the frame's transfer functions, zero-alpha runs,
+// channel parameters, per-level brick tables and per-level node tables in
+// LDS.  Ends with a workgroup barrier.
+template <int NV>
+__device__ __forceinline__ void stage_frame(const RenderArgs &A, float4 *s_tf, ChanLds *s_ch, uint32_t *s_runs,
+                                            LevLds *s_lv, NodeLds *s_nd) {
+    const int nvis = A.nvis;
+    for (int i = threadIdx.x; i < nvis * 256; i += blockDim.x) s_tf[i] = A.tf[i];
+    const unsigned t = threadIdx.x;
+    if (t < (unsigned)A.L) {
+        LevLds lv;
+        lv.raw = A.lsh[t];
+        lv.sh = lv.raw + (uint32_t)A.Blog * 0x010101u;
+        lv.loff = A.loff[t];
+        lv.nbx = A.nbx[t];
+        lv.nbxy = A.nbx[t] * A.nby[t];
+        lv.K = A.K[t];
+        s_lv[t] = lv;
+    }
+    if (t >= 64 && t < 64u + (unsigned)A.depth + 1u) {
+        const unsigned dl = t - 64;
+        NodeLds nd;
+        nd.nsh = A.nsh[dl];
+        nd.nlg = A.nlg[dl];
+        nd.noff = A.noff[dl];
+        s_nd[dl] = nd;
+    }
+    __syncthreads();
+    if (t < (unsigned)nvis) {
+        ChanLds ch;
+        ch.c = A.vis[t];
+        ch.lo = A.lo[t];
+        ch.hi = A.hi[t];
+        ch.w0 = A.w0[t];
+        ch.iw = A.iw[t];
+        ch.nruns = build_runs(s_tf + t * 256, A.W0[t], A.W1[t], s_runs + t * kMaxRuns);
+        s_ch[t] = ch;
+    }
+    __syncthreads();
+
+}
+
+}  // namespace ro

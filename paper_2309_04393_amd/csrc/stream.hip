@@ -131,6 +131,14 @@ __global__ void __launch_bounds__(256) k_req_write(uint32_t *__restrict__ cnt, u
 
 ro_status read_requests_device(ro_cache *c, uint32_t cap, uint32_t *ids, uint32_t *counts,
                                uint32_t *n_unique, uint64_t *total, hipStream_t s) {
+    return compact_dense(c, c->b.counters, cap, ids, counts, n_unique, total, s);
+}
+
+// Compacts a dense per-brick u32 array into (ID, value) pairs of its nonzero
+// entries in ascending ID order (at most cap returned), with the distinct
+// count and the sum, and clears the array.  Synchronises.
+ro_status compact_dense(ro_cache *c, uint32_t *arr, uint32_t cap, uint32_t *ids, uint32_t *counts,
+                        uint32_t *n_unique, uint64_t *total, hipStream_t s) {
     const VolGeo &g = c->vol->g;
     uint8_t *sc = (uint8_t *)c->b.scratch;
     uint32_t nblk = c->sc.nblk;
@@ -139,11 +147,11 @@ ro_status read_requests_device(ro_cache *c, uint32_t cap, uint32_t *ids, uint32_
     unsigned long long *tot = (unsigned long long *)(sc + c->sc.sel);
     uint32_t *pairs = (uint32_t *)(sc + c->sc.outpairs);
     RO_HIP(hipMemsetAsync(tot, 0, 8, s));
-    hipLaunchKernelGGL(k_req_count, dim3(nblk), dim3(256), 0, s, c->b.counters, g.total, blk, tot);
+    hipLaunchKernelGGL(k_req_count, dim3(nblk), dim3(256), 0, s, arr, g.total, blk, tot);
     RO_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, s, blk, nblk, offs);
     RO_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_req_write, dim3(nblk), dim3(256), 0, s, c->b.counters, g.total, offs, g, pairs);
+    hipLaunchKernelGGL(k_req_write, dim3(nblk), dim3(256), 0, s, arr, g.total, offs, g, pairs);
     RO_HIP(hipGetLastError());
     uint32_t nu = 0;
     unsigned long long t = 0;

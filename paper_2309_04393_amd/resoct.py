@@ -106,6 +106,14 @@ _sig("ro_octree_set_leaf_metadata", c_i32, [c_vp, c_u32, c_vp, c_vp])
 _sig("ro_update_residency", c_i32, [c_vp, c_vp])
 _sig("ro_rebuild_residency", c_i32, [c_vp, c_vp])
 _sig("ro_render", c_i32, [c_vp, _P(FrameDesc), c_vp, c_vp])
+_sig("ro_mlp_query", c_i32, [_P(c_sz), _P(c_sz)])
+_sig("ro_mlp_create", c_i32, [c_vp, c_vp, _P(c_vp)])
+_sig("ro_mlp_destroy", None, [c_vp])
+_sig("ro_mlp_set_weights", c_i32, [c_vp, c_vp, c_vp])
+_sig("ro_mlp_get_weights", c_i32, [c_vp, c_vp, c_vp])
+_sig("ro_mlp_forward", c_i32, [c_vp, c_vp, c_u32, c_vp, c_vp])
+_sig("ro_mlp_gradients", c_i32, [c_vp, c_vp, c_vp, c_vp, c_u32, c_vp, c_vp, c_vp])
+_sig("ro_mlp_train_step", c_i32, [c_vp, c_vp, c_vp, c_vp, c_u32, ctypes.c_float, c_vp, c_vp])
 
 
 class ResoctError(RuntimeError):
@@ -348,3 +356,117 @@ def frame_desc(frame: int, cam: dict, W: int, H: int, step: float, channels: lis
     fd.aov_dev = aov.data_ptr() if aov is not None else None
     fd.stats_dev = stats.data_ptr() if stats is not None else None
     return fd
+
+
+MLP_KEYS = (("W1", (24, 64)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (64, 9)), ("b3", (9,)))
+
+
+def _pack_weights(p: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(p[k], np.float32).reshape(-1) for k, _ in MLP_KEYS])
+
+
+def _unpack_weights(flat: np.ndarray) -> dict:
+    out, o = {}, 0
+    for k, shp in MLP_KEYS:
+        n = int(np.prod(shp))
+        out[k] = flat[o:o + n].reshape(shp).copy()
+        o += n
+    return out
+
+
+class Mlp:
+    """The request predictor's parameters and optimiser state on the device."""
+
+    def __init__(self, device="cuda"):
+        pb, wb = c_sz(), c_sz()
+        _check(_lib.ro_mlp_query(ctypes.byref(pb), ctypes.byref(wb)), "ro_mlp_query")
+        self.params = _alloc(pb.value, device)
+        self.work = _alloc(wb.value, device)
+        h = c_vp()
+        _check(_lib.ro_mlp_create(_dev_ptr(self.params), _dev_ptr(self.work), ctypes.byref(h)), "ro_mlp_create")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.ro_mlp_destroy(self.h)
+            self.h = None
+
+    def set_weights(self, p: dict, stream=None):
+        flat = np.ascontiguousarray(_pack_weights(p))
+        _check(_lib.ro_mlp_set_weights(self.h, _np_ptr(flat), _stream(stream)), "ro_mlp_set_weights")
+
+    def get_weights(self, stream=None) -> dict:
+        flat = np.zeros(sum(int(np.prod(s)) for _, s in MLP_KEYS), np.float32)
+        _check(_lib.ro_mlp_get_weights(self.h, _np_ptr(flat), _stream(stream)), "ro_mlp_get_weights")
+        return _unpack_weights(flat)
+
+    def forward(self, x: torch.Tensor, z: torch.Tensor = None, stream=None) -> torch.Tensor:
+        assert x.dtype == torch.float16 and x.is_contiguous() and x.shape[1] == 32
+        rows = x.shape[0]
+        z = torch.empty((rows, 16), dtype=torch.float32, device=x.device) if z is None else z
+        _check(_lib.ro_mlp_forward(self.h, _dev_ptr(x), rows, _dev_ptr(z), _stream(stream)), "ro_mlp_forward")
+        return z
+
+    def gradients(self, x, y, mask, stream=None):
+        flat = np.zeros(sum(int(np.prod(s)) for _, s in MLP_KEYS), np.float32)
+        loss = ctypes.c_float()
+        _check(_lib.ro_mlp_gradients(self.h, _dev_ptr(x), _dev_ptr(y), _dev_ptr(mask), x.shape[0], _np_ptr(flat),
+                                     ctypes.byref(loss), _stream(stream)), "ro_mlp_gradients")
+        return _unpack_weights(flat), float(loss.value)
+
+    def train_step(self, x, y, mask, lr: float, want_loss=False, stream=None):
+        loss = ctypes.c_float()
+        _check(_lib.ro_mlp_train_step(self.h, _dev_ptr(x), _dev_ptr(y), _dev_ptr(mask), x.shape[0], lr,
+                                      ctypes.byref(loss) if want_loss else None, _stream(stream)),
+               "ro_mlp_train_step")
+        return float(loss.value) if want_loss else None
+
+
+_sig("ro_pf_query", c_i32, [c_vp, _P(c_u32), _P(c_sz), _P(c_sz)])
+_sig("ro_pf_create", c_i32, [c_vp, c_vp, c_vp, c_vp, _P(c_vp)])
+_sig("ro_pf_destroy", None, [c_vp])
+_sig("ro_pf_record", c_i32, [c_vp, c_u32, c_vp])
+_sig("ro_pf_features", c_i32, [c_vp, _P(FrameDesc), c_vp, c_vp])
+_sig("ro_pf_labels", c_i32, [c_vp, c_vp, c_vp, c_vp])
+_sig("ro_pf_candidates", c_i32, [c_vp, c_vp, ctypes.c_float, c_u32, c_vp, c_vp, _P(c_u32), c_vp])
+
+
+class PrefetchRows:
+    """Predictor rows, brick history and candidate scores of one octree."""
+
+    def __init__(self, tree: Octree, device="cuda", stream=None):
+        rows, hb, sb = c_u32(), c_sz(), c_sz()
+        _check(_lib.ro_pf_query(tree.h, ctypes.byref(rows), ctypes.byref(hb), ctypes.byref(sb)), "ro_pf_query")
+        self.rows = int(rows.value)
+        self.hist = _alloc(hb.value, device)
+        self.score = _alloc(sb.value, device)
+        h = c_vp()
+        _check(_lib.ro_pf_create(tree.h, _dev_ptr(self.hist), _dev_ptr(self.score), _stream(stream),
+                                 ctypes.byref(h)), "ro_pf_create")
+        self.h = h
+        self.tree = tree
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.ro_pf_destroy(self.h)
+            self.h = None
+
+    def record(self, frame: int, stream=None):
+        _check(_lib.ro_pf_record(self.h, frame, _stream(stream)), "ro_pf_record")
+
+    def features(self, fd: FrameDesc, x: torch.Tensor, stream=None):
+        assert x.dtype == torch.float16 and x.shape == (self.rows, 32)
+        _check(_lib.ro_pf_features(self.h, ctypes.byref(fd), _dev_ptr(x), _stream(stream)), "ro_pf_features")
+
+    def labels(self, y: torch.Tensor, mask: torch.Tensor, stream=None):
+        assert y.shape == (self.rows, 16) and mask.shape == (self.rows, 16)
+        _check(_lib.ro_pf_labels(self.h, _dev_ptr(y), _dev_ptr(mask), _stream(stream)), "ro_pf_labels")
+
+    def candidates(self, z: torch.Tensor, threshold=0.5, cap=1 << 16, stream=None):
+        ids = np.zeros(max(cap, 1), np.uint32)
+        pr = np.zeros(max(cap, 1), np.float32)
+        n = c_u32()
+        _check(_lib.ro_pf_candidates(self.h, _dev_ptr(z), threshold, cap, _np_ptr(ids), _np_ptr(pr), ctypes.byref(n),
+                                     _stream(stream)), "ro_pf_candidates")
+        k = min(cap, n.value)
+        return ids[:k], pr[:k]

@@ -429,3 +429,18 @@ def config2_volume(seed=2, dims=(2048, 2048, 64), n_channels=4):
 
 def config3_volume(seed=3, dims=(8192, 8192, 192), n_channels=16):
     return CellVolume(dims, n_channels, spacing=(1, 1, 3), n_levels=9, seed=seed, tissue=True)
+
+
+# ------------------------------------------------------------ network init
+
+def mlp_init(seed=7, sizes=(24, 64, 64, 9)):
+    """Seeded initial weights of the request predictor (He-uniform for the
+    ReLU layers, small output layer, zero biases), float32, input-major."""
+    rng = np.random.default_rng(seed)
+    p = {}
+    for i in range(3):
+        fan_in, fan_out = sizes[i], sizes[i + 1]
+        lim = math.sqrt(6.0 / fan_in) * (0.25 if i == 2 else 1.0)
+        p[f"W{i + 1}"] = rng.uniform(-lim, lim, size=(fan_in, fan_out)).astype(np.float32)
+        p[f"b{i + 1}"] = np.zeros(fan_out, np.float32)
+    return p

@@ -61,7 +61,7 @@ class Pair:
         m_or = oracle.masks(self.V, self.sim.res_slot)
         assert np.array_equal(m_gpu, m_or), f"masks differ at {np.argwhere(m_gpu != m_or)[:5]}"
 
-    def frame(self, f, cam, W, H, step, chans, term_margin=2e-6, aov=False, **kw):
+    def frame(self, f, cam, W, H, step, chans, term_margin=1e-6, aov=False, **kw):
         r = self.gpu.render(f, cam, W, H, step, chans, aov=aov, **kw)
         torch.cuda.synchronize()
         ids, cnt, nu, tot = self.gpu.cache.read_requests(1 << 20)
@@ -102,7 +102,7 @@ def test_cfg1_full_resident_axis_view(cfg1):
     p.check_page_table()
     p.check_masks()
     cam = synth.camera_ortho_axis((64, 64), 128, 128)
-    res = p.frame(1, cam, 128, 128, 0.5, _cfg1_chans(0, 0), term_margin=2e-6, aov=True)
+    res = p.frame(1, cam, 128, 128, 0.5, _cfg1_chans(0, 0), term_margin=1e-6, aov=True)
     p.check_frame(res, "cfg1-axis")
     assert res["tot"] == 0
     assert np.array_equal(res["aov"], res["o"]["aov"]) or (res["o"]["amb_pix"].any())
@@ -137,7 +137,7 @@ def test_cfg1_substitution_levels(cfg1):
     p.upload(0, ids)
     p.check_masks()
     cam = synth.camera_ortho_axis((64, 64), 128, 128)
-    res = p.frame(1, cam, 128, 128, 0.5, _cfg1_chans(0, 0), term_margin=2e-6, aov=True)
+    res = p.frame(1, cam, 128, 128, 0.5, _cfg1_chans(0, 0), term_margin=1e-6, aov=True)
     p.check_frame(res, "cfg1-substitution")
     assert res["aov"][..., 0].sum() == 0
     assert res["aov"][..., 1].sum() > 0 and res["aov"][..., 2].sum() > 0

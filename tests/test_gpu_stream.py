@@ -1,0 +1,170 @@
+"""GPU parity of the streaming side: multi-frame request-driven loop, LRU
+batches, page tables, residency masks, metadata reduction, capped readback,
+host-forced corruption + rebuild, checkpoint / restore determinism."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import compare_images, compare_requests, compare_usage, gpu_rgba
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from tests.test_gpu_render import Pair, _report  # noqa: E402
+
+
+def _cells(dims=(512, 512, 64), n_ch=4, n_levels=6, seed=2):
+    src = synth.CellVolume(dims, n_ch, spacing=(1, 1, 4), n_levels=n_levels, seed=seed)
+    src.levels = [[src.level_array(c, l) for l in range(n_levels)] for c in range(n_ch)]
+    return src
+
+
+def _chans(n, lo=0, hi=5):
+    return [dict(c=c, lo=lo, hi=hi, W0=300 * 256, W1=8000 * 256, tf=synth.tf_hue(c / n, 0.1)) for c in range(n)]
+
+
+def _plain(ids, cnt, U):
+    order = np.lexsort((ids, -cnt.astype(np.int64)))
+    return ids[order][:U]
+
+
+@pytest.fixture(scope="module")
+def cells():
+    return _cells()
+
+
+def test_streaming_loop_matches_oracle(cells):
+    """Six frames of an orbit from a cold, too-small cache: every frame's
+    image, request multiset and usage set, the plain policy's upload list,
+    the LRU batch (flags, page table) and the residency masks agree."""
+    p = Pair(cells, 32, (16, 16, 4), 5, n_slots=300, max_batch=128)
+    cams = synth.orbit_path(cells.dims, cells.spacing, 8, az_step_deg=9.0)
+    chans = _chans(4)
+    for f in range(1, 7):
+        res = p.frame(f, cams[f], 96, 96, 0.5, chans, lod_bias=0.7)
+        p.check_frame(res, f"loop-{f}")
+        g_up = _plain(res["ids"], res["cnt"], 128)
+        o_up = p.sim.plain_policy(res["o"]["counts"], 128)
+        assert np.array_equal(g_up, p.ids[o_up]), "plain policy differs"
+        p.upload(f, g_up)
+        p.check_page_table()
+        p.check_masks()
+
+
+def test_metadata_reduction_matches_oracle(cells):
+    p = Pair(cells, 32, (16, 16, 4), 5, n_slots=8)
+    torch.cuda.synchronize()
+    assert np.array_equal(p.gpu.tree.meta(), oracle.meta_all(p.V, p.leaf_mm))
+
+
+def test_capped_readback(cells):
+    """Sec. 4 global limit: the first `cap` pairs in ascending ID, with the
+    full distinct count and total, then the counters are clear."""
+    p = Pair(cells, 32, (16, 16, 4), 5, n_slots=8)
+    cam = synth.orbit_path(cells.dims, cells.spacing, 2)[1]
+    chans = _chans(4)
+    p.gpu.render(1, cam, 64, 64, 0.5, chans)
+    torch.cuda.synchronize()
+    ids, cnt, nu, tot = p.gpu.cache.read_requests(5)
+    fr, keep = oracle.make_frame(cam, 64, 64, 0.5, chans, term_margin=1e-6)
+    o = oracle.render(p.V, cells.levels, p.sim.res_slot, p.leaf_mm, fr, p.S)
+    nz = np.nonzero(o["counts"])[0]
+    o_ids = np.sort(p.ids[nz])
+    assert o["amb_counts"].sum() == 0
+    assert nu == len(nz) and tot == int(o["counts"].sum())
+    assert np.array_equal(ids, o_ids[:5])
+    ids2, cnt2, nu2, tot2 = p.gpu.cache.read_requests(5)
+    assert nu2 == 0 and tot2 == 0 and len(ids2) == 0
+
+
+def test_rebuild_after_corrupted_masks(cells):
+    """Host-forced fault: garbage written into the node masks is repaired by
+    the from-scratch rebuild, which equals the oracle's masks."""
+    p = Pair(cells, 32, (16, 16, 4), 5, n_slots=120, max_batch=128)
+    rng = np.random.default_rng(5)
+    ids = p.gpu.all_ids()
+    rng.shuffle(ids)
+    p.upload(0, ids[:100])
+    p.check_masks()
+    m = p.gpu.tree.t["node_mask"]
+    m.copy_(torch.randint(0, 255, m.shape, dtype=torch.uint8, device=m.device))
+    p.gpu.tree.rebuild_residency()
+    torch.cuda.synchronize()
+    assert np.array_equal(p.gpu.tree.masks(), oracle.masks(p.V, p.sim.res_slot))
+
+
+def test_invalid_ids_leave_state_unchanged(cells):
+    from paper_2309_04393_amd import resoct
+    p = Pair(cells, 32, (16, 16, 4), 5, n_slots=16, max_batch=32)
+    ids = p.gpu.all_ids()[:4]
+    p.upload(0, ids)
+    before = p.gpu.cache.page_table_host().copy()
+    bad = np.array([ids[0], 0x00FF0000], np.uint32)  # bz = 255 does not exist
+    with pytest.raises(resoct.ResoctError) as e:
+        p.gpu.cache.stream_bricks(1, bad, p.gpu.stage(ids[:2]))
+    assert e.value.code == -1
+    assert np.array_equal(p.gpu.cache.page_table_host(), before)
+    many = p.gpu.all_ids()[:40]
+    with pytest.raises(resoct.ResoctError) as e:
+        p.gpu.cache.stream_bricks(1, many, p.gpu.cache.staging(len(many)))  # more than max_batch
+    assert e.value.code == -1 and "max_batch" in str(e.value)
+    assert np.array_equal(p.gpu.cache.page_table_host(), before)
+
+
+def test_checkpoint_restore_replays_identically(cells):
+    p = Pair(cells, 32, (16, 16, 4), 5, n_slots=200, max_batch=128)
+    cams = synth.orbit_path(cells.dims, cells.spacing, 6, az_step_deg=12.0)
+    chans = _chans(4)
+    g = p.gpu
+
+    def run(frames):
+        outs = []
+        for f in frames:
+            r = g.render(f, cams[f], 64, 64, 0.5, chans)
+            torch.cuda.synchronize()
+            ids, cnt, nu, tot = g.cache.read_requests(1 << 16)
+            up = _plain(ids, cnt, 128)
+            fl = g.upload(f, up)
+            g.tree.update_residency()
+            outs.append((r["rgba"].cpu().numpy().copy(), ids.copy(), cnt.copy(), fl.copy()))
+        return outs
+
+    run([1, 2])
+    dev = {("c", k): v.clone() for k, v in g.cache.t.items()}
+    dev.update({("t", k): v.clone() for k, v in g.tree.t.items()})
+    host = g.cache.save_state()
+    a = run([3, 4, 5])
+    for (kind, k), v in dev.items():
+        (g.cache.t if kind == "c" else g.tree.t)[k].copy_(v)
+    torch.cuda.synchronize()
+    g.cache.load_state(host)
+    b = run([3, 4, 5])
+    for x, y in zip(a, b):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v)
+
+
+def test_run_is_deterministic(cells):
+    """Determinism is the race test: the same frame twice gives identical
+    counters, stamps, masks and page tables."""
+    outs = []
+    for _ in range(2):
+        p = Pair(cells, 32, (16, 16, 4), 5, n_slots=150, max_batch=128)
+        ids = p.gpu.all_ids()
+        np.random.default_rng(1).shuffle(ids)
+        p.upload(0, ids[:140])
+        p.gpu.tree.update_residency()
+        cam = synth.orbit_path(cells.dims, cells.spacing, 3)[2]
+        r = p.gpu.render(1, cam, 80, 80, 0.5, _chans(4))
+        torch.cuda.synchronize()
+        rq = p.gpu.cache.read_requests(1 << 16)
+        outs.append((r["rgba"].cpu().numpy(), rq[0], rq[1], p.gpu.cache.t["stamps"].cpu().numpy(),
+                     p.gpu.tree.masks(), p.gpu.cache.page_table_host()))
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)
