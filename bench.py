@@ -255,6 +255,88 @@ def scene_leaf_mm(cfg, V=None):
     return leaf_mm_all(cfg)
 
 
+def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True):
+    """Serving on the 16-channel 2048 x 2048 x 64 cell volume, every brick
+    resident in a 24 GiB cache: 64 clients, Poisson arrivals at `rate`
+    requests/s, viewports {256^2, 512^2, 1024^2, 1920x1080}, 3-16 channels
+    per request, per-client transfer functions and camera paths.  Measures
+    the throughput of n_sat such requests batched (all queued at once) and
+    one request at a time through the frame kernel, then p50/p99 latency over
+    `seconds` of arrivals at `rate` and at 70% of the batched capacity (a
+    request still unfinished 5 s after the arrivals stop counts as
+    infinitely late)."""
+    import torch
+
+    import synth
+    from paper_2309_04393_amd.pipeline import GpuScene
+    from paper_2309_04393_amd.serving import ServingLoop, latency_summary, make_trace, reset_trace
+    vol = synth.config2_volume(n_channels=16)
+    t = time.perf_counter()
+    stride = 78848
+    n_slots = (24 << 30) // stride
+    scene = GpuScene(vol, 32, (16, 16, 4), 7, n_slots, max_batch=4096, start_level=2, set_metadata=False)
+    lg = leaf_grid(vol.dims, (16, 16, 4), 7)
+    mx = vol.leaf_max_all((16, 16, 4), lg)
+    for c in range(vol.n_channels):
+        mm = np.zeros((mx.shape[1], 2), np.uint16)
+        mm[:, 1] = mx[c]
+        scene.set_metadata(c, mm)
+    ids = scene.all_ids()
+    scene.upload(0, ids)
+    scene.tree.update_residency()
+    torch.cuda.synchronize()
+    log(f"serving scene: {len(ids)} bricks resident in {n_slots} slots ({time.perf_counter() - t:.1f} s)")
+    loop = ServingLoop(scene, out_budget=4 << 30, max_requests=64, max_tiles=1 << 17, graph=graph)
+    from paper_2309_04393_amd import resoct
+    # saturated throughput: the same requests batched vs one at a time
+    sub = make_trace(scene, rate, n_sat / rate, arrival_seed=3001)
+    for r in sub:
+        r.arrival = 0.0
+    loop.run(sub[:16])  # graph capture, first-touch
+    reset_trace(sub)
+    loop.stats.zero_()
+    wb = loop.run(sub)
+    sb = float(loop.stats.cpu().numpy()[0])
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    img = torch.empty(4 * 1920 * 1080, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for r in sub:
+        fd = resoct.frame_desc(r.frame, r.cam, r.W, r.H, loop.step, r.chans, r.tf, scene.vol.n_levels,
+                               stats=stats)
+        scene.tree.render(fd, img)
+    torch.cuda.synchronize()
+    ws = time.perf_counter() - t
+    ss = float(stats.cpu().numpy()[0])
+    out = {"workload": "16ch-2048x2048x64-u16 cells, all 173392 bricks resident, 24 GiB cache",
+           "clients": 64, "graph": graph,
+           "saturated": {"requests": len(sub), "batched_samples_per_s": sb / wb, "batched_req_per_s": len(sub) / wb,
+                         "one_at_a_time_samples_per_s": ss / ws, "one_at_a_time_req_per_s": len(sub) / ws,
+                         "speedup": (sb / wb) / (ss / ws), "same_samples": sb == ss}}
+    cap = len(sub) / wb
+
+    def at_rate(lam, seed):
+        trace = make_trace(scene, lam, seconds, arrival_seed=seed)
+        loop.stats.zero_()
+        nb0 = loop.n_batches
+        wall = loop.run(trace, deadline=seconds + 5.0)
+        st = loop.stats.cpu().numpy()
+        lat = latency_summary(trace)
+        sizes = loop.batch_sizes[nb0:]
+        done = sum(1 for r in trace if np.isfinite(r.done))
+        return {"rate_req_per_s": lam, "seconds": seconds, "requests": len(trace), "completed": done,
+                "latency_ms": {k: v for k, v in lat.items() if k not in ("n", "completed")},
+                "wall_s": wall, "served_req_per_s": done / wall, "samples_per_s": float(st[0]) / wall,
+                "batches": len(sizes), "mean_batch": float(np.mean(sizes)) if sizes else 0.0}
+
+    out["stated_load"] = at_rate(rate, 3000)
+    out["load_70pct_capacity"] = at_rate(0.7 * cap, 3002)
+    log(f"serving: {json.dumps(out)}")
+    del loop, scene
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +345,10 @@ def main():
     ap.add_argument("--config", default="cfg3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=192)
+    ap.add_argument("--serve", type=float, default=10.0, metavar="SECONDS",
+                    help="seconds of the serving measurement after the frame measurement (0: skip)")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving measurement")
+    ap.add_argument("--rate", type=float, default=400.0, help="serving arrival rate, requests/s")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the measurement, copy a 1 GiB buffer three times (a plain copy kernel of "
                          "known size, to scale hardware byte counters)")
@@ -276,6 +362,9 @@ def main():
     import synth
     from paper_2309_04393_amd.pipeline import GpuScene
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.serve_only:
+        print(json.dumps({"serving": serve_bench(args.rate, args.serve)}), flush=True)
+        return
     cfg = config(args.config)
     vol = cfg["vol"]
     t_setup = time.perf_counter()
@@ -390,6 +479,10 @@ def main():
             out["cpu_baseline"] = cb
         except Exception as e:  # reported, not fatal
             out["cpu_baseline"] = {"error": repr(e)}
+    if args.serve > 0:
+        del fl, store, scene
+        torch.cuda.empty_cache()
+        out["serving"] = serve_bench(args.rate, args.serve)
     print(json.dumps(out), flush=True)
 
 

@@ -359,6 +359,55 @@ ro_status ro_pf_labels(ro_prefetch *p, uint8_t *y_dev, uint8_t *mask_dev, void *
 ro_status ro_pf_candidates(ro_prefetch *p, const float *z_dev, float threshold, uint32_t cap, uint32_t *ids_host,
                            float *prob_host, uint32_t *n_out, void *stream);
 
+/* --------------------------------------------------------------- serving */
+
+/* Batched rendering for a serving loop (an addition to the paper's method):
+ * one persistent kernel renders up to 64 frame requests of different
+ * viewports, channel subsets, transfer functions and cameras over the shared
+ * cache and octree; its workgroups pop 32 x 16-pixel tiles from a device
+ * queue.  Each pixel runs the same code as ro_render, so a request's image is
+ * the same alone and in any batch.
+ *
+ * A server owns pinned host memory for two batches ("halves", used
+ * alternately) and two non-blocking streams of default priority, one per
+ * half; the caller owns the device buffer (size from ro_serve_query, 256-byte
+ * aligned) that holds the halves' device copies and queue counters.  Batches
+ * from different halves may run concurrently.  The serving kernel reads the
+ * cache and octree and adds to the request counters; the caller must not
+ * stream bricks or update residency while a batch is in flight (wait for its
+ * ticket), and usage stamps written by overlapping batches of different frame
+ * numbers end with either value.  Not thread-safe. */
+#define RO_SERVE_GRAPH 1u
+typedef struct ro_server ro_server;
+ro_status ro_serve_query(uint32_t max_requests, uint32_t max_tiles, size_t *device_bytes);
+/* max_requests in 1..64 per batch; max_tiles in 1..2^24 per batch. */
+ro_status ro_serve_create(ro_octree *t, uint32_t max_requests, uint32_t max_tiles, void *device_buf,
+                          ro_server **out);
+/* Waits for outstanding batches, then frees the server's resources. */
+void ro_serve_destroy(ro_server *s);
+/* Host side of a batch: fds[n] as for ro_render (no AOV), rgba_dev[n] output
+ * images ([H][W][4] float, 256-byte aligned).  Writes the next half after
+ * waiting for that half's previous batch to finish.  full_channels != 0
+ * selects the 16-channel kernel whatever the batch holds, which graph
+ * submission requires.  RO_E_CAPACITY when n or the batch's tiles exceed the
+ * server's limits, RO_E_STATE when a prepared batch is still unsubmitted;
+ * nothing is submitted on error. */
+ro_status ro_serve_prepare(ro_server *s, uint32_t n, const ro_frame_desc *fds, float *const *rgba_dev,
+                           int32_t full_channels);
+/* Device side: on the half's stream, copy the prepared half to its device
+ * copy, reset its queue and run the kernel.  With RO_SERVE_GRAPH the sequence
+ * is captured into a graph on the half's first such submission and replayed
+ * afterwards (it depends only on the half).  *ticket (may be null) names the
+ * batch for ro_serve_poll / ro_serve_wait. */
+ro_status ro_serve_submit(ro_server *s, uint32_t flags, uint64_t *ticket);
+/* *done = 1 when the batch has finished (its images and counters are
+ * written), else 0. */
+ro_status ro_serve_poll(ro_server *s, uint64_t ticket, int32_t *done);
+ro_status ro_serve_wait(ro_server *s, uint64_t ticket);
+/* prepare (kernel chosen by the batch's largest channel count) + submit. */
+ro_status ro_serve_launch(ro_server *s, uint32_t n, const ro_frame_desc *fds, float *const *rgba_dev,
+                          uint64_t *ticket);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char *ro_last_error(void);
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libresoct.so")
-SOURCES = ["api.hip", "render.hip", "stream.hip", "octree.hip", "mlp.hip", "prefetch.hip"]
+SOURCES = ["api.hip", "render.hip", "stream.hip", "octree.hip", "mlp.hip", "prefetch.hip", "serve.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

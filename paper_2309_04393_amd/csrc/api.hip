@@ -516,7 +516,9 @@ extern "C" ro_status ro_rebuild_residency(ro_octree *t, void *stream) {
     return RO_OK;
 }
 
-extern "C" ro_status ro_render(ro_octree *t, const ro_frame_desc *fd, float *rgba, void *stream) {
+namespace ro {
+// Frame validation shared by ro_render and the serving launch.
+ro_status validate_frame(const ro_octree *t, const ro_frame_desc *fd, const float *rgba) {
     RO_CHECK(t && fd && rgba, RO_E_ARG, "null argument");
     const VolGeo &g = t->cache->vol->g;
     RO_CHECK(aligned(rgba), RO_E_ARG, "rgba must be 256-byte aligned");
@@ -542,5 +544,12 @@ extern "C" ro_status ro_render(ro_octree *t, const ro_frame_desc *fd, float *rgb
         RO_CHECK(fd->win_lo[j] < fd->win_hi[j] && fd->win_hi[j] <= (uint32_t)(65535u * 256u),
                  RO_E_ARG, "bad window for visible slot %d", j);
     }
+    return RO_OK;
+}
+}  // namespace ro
+
+extern "C" ro_status ro_render(ro_octree *t, const ro_frame_desc *fd, float *rgba, void *stream) {
+    ro_status st = validate_frame(t, fd, rgba);
+    if (st) return st;
     return render_device(t, fd, rgba, (hipStream_t)stream);
 }

@@ -151,4 +151,5 @@ ro_status octree_update(ro_octree *t, const std::vector<uint32_t> &dirty, hipStr
 ro_status octree_rebuild(ro_octree *t, hipStream_t s);
 
 ro_status render_device(ro_octree *t, const ro_frame_desc *fd, float *rgba, hipStream_t s);
+ro_status validate_frame(const ro_octree *t, const ro_frame_desc *fd, const float *rgba);
 }  // namespace ro

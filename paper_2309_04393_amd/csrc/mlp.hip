@@ -449,7 +449,6 @@ extern "C" void ro_mlp_destroy(ro_mlp *n) { delete n; }
 
 // Host weight layout (unpadded): W1[24][64], b1[64], W2[64][64], b2[64],
 // W3[64][9], b3[9].
-static const int kHostN = 24 * 64 + 64 + 64 * 64 + 64 + 64 * 9 + 9;
 
 extern "C" ro_status ro_mlp_set_weights(ro_mlp *n, const float *host, void *stream) {
     RO_CHECK(n && host, RO_E_ARG, "null argument");

@@ -1,7 +1,7 @@
 // Ray-guided mixed-resolution multi-channel ray casting over the residency
 // octree (Sec. 6.1, Alg. 1; Sec. 6.2; Sec. 6 implementation notes).
 //
-// One lane per pixel; a 256-lane workgroup covers a 16 x 16 pixel tile.
+// One lane per pixel; a 512-lane workgroup covers a 32 x 16 pixel tile.
 // Sample positions and every integer decision derived from them (box, leaf,
 // brick, level) are computed in FP64; interpolation, transfer functions and
 // the channel mix in FP32; the compositing state in FP64.  Per lane, the
@@ -22,7 +22,7 @@
 namespace ro {
 
 template <int NV, int BPV, bool AOV>
-__global__ void __launch_bounds__(256) k_render(const RenderArgs A) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_render(const RenderArgs A) {
     extern __shared__ float4 s_tf[];  // [nvis][256]
     __shared__ ChanLds s_ch[NV];
     __shared__ uint32_t s_runs[NV * kMaxRuns];
@@ -31,10 +31,12 @@ __global__ void __launch_bounds__(256) k_render(const RenderArgs A) {
 
     stage_frame<NV>(A, s_tf, s_ch, s_runs, s_lv, s_nd);
 
-    const int px = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int py = blockIdx.y * 16 + (threadIdx.x >> 4);
+    // 32 x 16 pixels per workgroup, 8 x 8 pixels per wave
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int px = blockIdx.x * 32 + (wv & 3) * 8 + (ln & 7);
+    const int py = blockIdx.y * 16 + (wv >> 2) * 8 + (ln >> 3);
     uint32_t st[5] = {0, 0, 0, 0, 0};
-    if (px < A.W && py < A.H) render_pixel<NV, BPV, AOV>(A, px, py, s_tf, s_ch, s_runs, s_lv, s_nd, st);
+    render_pixel<NV, BPV, AOV>(A, px, py, px < A.W && py < A.H, s_tf, s_ch, s_runs, s_lv, s_nd, st);
     if (A.stats) {
         // every lane of the workgroup is here: reduce over the wave, one atomic per wave
 #pragma unroll
@@ -52,7 +54,7 @@ static hipError_t launch_one(const RenderArgs &A, dim3 grid, size_t lds, hipStre
     hipError_t e = hipFuncSetAttribute((const void *)k_render<NV, BPV, AOV>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_render<NV, BPV, AOV>), grid, dim3(256), lds, s, A);
+    hipLaunchKernelGGL((k_render<NV, BPV, AOV>), grid, dim3(512), lds, s, A);
     return hipGetLastError();
 }
 
@@ -70,11 +72,11 @@ static hipError_t launch_bpv(const RenderArgs &A, bool aov, dim3 grid, size_t ld
     return launch_nv<16, BPV>(A, aov, grid, lds, s);
 }
 
-ro_status render_device(ro_octree *tr, const ro_frame_desc *fd, float *rgba, hipStream_t s) {
+// Kernel arguments of one frame (validated by the caller).
+ro_status build_render_args(ro_octree *tr, const ro_frame_desc *fd, float *rgba, RenderArgs &A) {
     const ro_cache *c = tr->cache;
     const VolGeo &g = c->vol->g;
     const TreeGeo &T = tr->t;
-    RenderArgs A;
     memset(&A, 0, sizeof(A));
     for (int k = 0; k < 3; ++k) {
         A.dims[k] = g.dims[k];
@@ -154,7 +156,15 @@ ro_status render_device(ro_octree *tr, const ro_frame_desc *fd, float *rgba, hip
     A.rgba = rgba;
     A.aov = fd->aov_dev;
     A.stats = fd->stats_dev;
-    dim3 grid((fd->width + 15) / 16, (fd->height + 15) / 16);
+    return RO_OK;
+}
+
+ro_status render_device(ro_octree *tr, const ro_frame_desc *fd, float *rgba, hipStream_t s) {
+    const VolGeo &g = tr->cache->vol->g;
+    RenderArgs A;
+    ro_status st = build_render_args(tr, fd, rgba, A);
+    if (st) return st;
+    dim3 grid((fd->width + 31) / 32, (fd->height + 15) / 16);
     const size_t lds = sizeof(float4) * 256 * (size_t)fd->n_vis;
     const bool aov = (fd->flags & RO_RENDER_AOV) != 0;
     RO_HIP(g.bpv == 1 ? launch_bpv<1>(A, aov, grid, lds, s) : launch_bpv<2>(A, aov, grid, lds, s));

@@ -112,7 +112,8 @@ __device__ __forceinline__ uint32_t node_at(const NodeLds &nd, int x, int y, int
 }
 
 template <int NV, int BPV, bool AOV>
-__device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, const int py, const float4 *s_tf,
+__device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, const int py, const bool valid,
+                                             const float4 *s_tf,
                                              const ChanLds *s_ch, const uint32_t *s_runs, const LevLds *s_lv,
                                              const NodeLds *s_nd, uint32_t stats[5]) {
     const int nvis = A.nvis;
@@ -152,7 +153,7 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
     }
     double Cr = 0, Cg = 0, Cb = 0, Tr = 1.0;
     const double one_minus_term = 1.0 - (double)A.term;
-    float *out = A.rgba + ((size_t)py * A.W + px) * 4;
+    float *out = valid ? A.rgba + ((size_t)py * A.W + px) * 4 : nullptr;
 
     // ---- box interval
     double t0 = -INFINITY, t1 = INFINITY;
@@ -172,13 +173,14 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
         t0 = fmax(t0, u);
         t1 = fmin(t1, v);
     }
-    if (!hit || t0 > t1) {
-        out[0] = out[1] = out[2] = out[3] = 0.0f;
-        return;
-    }
-    long long k = (long long)floor(t0 / A.step) - 1;
+    // lanes whose ray misses the volume (or lie outside the image) stay in
+    // the loop below as inactive lanes: every lane of the wave takes part in
+    // the wave-level decisions
+    bool done = !valid || !hit || t0 > t1;
+    long long k = done ? 0 : (long long)floor(t0 / A.step) - 1;
     if (k < 0) k = 0;
-    const long long kend = (long long)ceil(t1 / A.step) + 1;
+    const long long kend = done ? -1 : (long long)ceil(t1 / A.step) + 1;
+    long long skip_to = 0;  // the lane is inside an empty node while k < skip_to
 
     // ---- visit state
     uint32_t cur_leaf = kInvalid;
@@ -215,7 +217,27 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
         nvisit = 0;
     };
 
-    while (k <= kend) {
+    // Wave-coherent stepping: lanes advance one sample per iteration, so the
+    // lanes of a wave (neighbouring pixels) sample at the same t and share
+    // cache lines; a lane inside an empty node idles, and the wave jumps
+    // ahead only by the smallest skip over its active lanes.  The samples a
+    // lane evaluates are exactly those it would evaluate on its own.
+    while (true) {
+        const bool active = !done && k <= kend;
+        const long long gap = skip_to - k;
+        uint32_t need = !active ? 0xFFFFFFFFu : (gap > 0 ? (gap < 0x7FFFFFFFll ? (uint32_t)gap : 0x7FFFFFFFu) : 0u);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) need = min(need, (uint32_t)__shfl_xor((int)need, o, 64));
+        if (need == 0xFFFFFFFFu) break;  // no active lane left in the wave
+        if (need > 0) {
+            k += need;
+            continue;
+        }
+        if (!active) continue;
+        if (k < skip_to) {
+            ++k;
+            continue;
+        }
         const double t = (double)k * A.step;
         double u[3];
         bool inside = true;
@@ -260,7 +282,8 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
                             te = fmin(te, (bound - o[a]) / d[a]);
                         }
                         const long long kn = (long long)floor(te / A.step) - 1;
-                        k = kn > k + 1 ? kn : k + 1;
+                        skip_to = kn > k + 1 ? kn : k + 1;
+                        ++k;
                         skipped = true;
                         break;
                     }
@@ -297,6 +320,7 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
                     }
                 }
                 slot[j] = ns;
+                asm volatile("" ::: "memory");
             }
         }
         ++nvisit;
@@ -355,6 +379,9 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
                 sbl += al * bb;
                 if (AOV) A.aov[((size_t)py * A.W + px) * L + lu] += 1;
             }
+            // keep one channel's gathers in flight at a time: bounds register
+            // pressure (occupancy) instead of interleaving all channels
+            asm volatile("" ::: "memory");
         }
         if (sa > 0.0f) {
             const float as = 1.0f - prod;
@@ -363,15 +390,17 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
             Cg += Tr * (double)(sg * sc);
             Cb += Tr * (double)(sbl * sc);
             Tr *= 1.0 - (double)as;
-            if (Tr <= one_minus_term) break;
+            if (Tr <= one_minus_term) done = true;
         }
         ++k;
     }
     flush();
-    out[0] = (float)Cr;
-    out[1] = (float)Cg;
-    out[2] = (float)Cb;
-    out[3] = (float)(1.0 - Tr);
+    if (out) {
+        out[0] = (float)Cr;
+        out[1] = (float)Cg;
+        out[2] = (float)Cb;
+        out[3] = (float)(1.0 - Tr);
+    }
     stats[0] = st_samples;
     stats[1] = st_reads;
     stats[2] = st_miss;

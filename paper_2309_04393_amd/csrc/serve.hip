@@ -1,0 +1,341 @@
+// Multi-request rendering for the serving loop (an addition to the paper's
+// method): one persistent kernel renders a batch of frame requests of
+// different viewports, channel subsets and transfer functions over the
+// shared cache and octree.  Workgroups pop 32 x 16-pixel tiles from a device
+// queue; when a tile belongs to another request than the previous one, the
+// workgroup stages that request's descriptor and tables in LDS.  Every pixel
+// runs the same per-ray code as the frame kernel, so a request's image does
+// not depend on what else is in the batch.
+//
+// The host prepares descriptors and the tile list in pinned host memory owned
+// by the server.  There are two halves used alternately, each with its own
+// device copy, queue counter and stream, so a batch can be prepared while the
+// previous one renders and the tail of one batch overlaps the head of the
+// next.  A submission copies the prepared half to the device and launches the
+// kernel with arguments that depend only on the half; with the 16-channel
+// kernel this sequence is captured once per half as a graph and replayed.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "render_core.h"
+
+namespace ro {
+
+// Batch header in the mapped buffer.
+struct ServeHeader {
+    uint32_t n_tiles;
+    uint32_t n_req;
+    uint32_t pad[62];
+};
+
+
+template <int NV, int BPV>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+    k_serve(const ServeHeader *__restrict__ hdr, const RenderArgs *__restrict__ descs,
+            const uint32_t *__restrict__ tiles, uint32_t *__restrict__ queue) {
+    extern __shared__ float4 s_tf[];  // [NV][256]
+    __shared__ RenderArgs sA;
+    __shared__ ChanLds s_ch[NV];
+    __shared__ uint32_t s_runs[NV * kMaxRuns];
+    __shared__ LevLds s_lv[kMaxL];
+    __shared__ NodeLds s_nd[kMaxD + 1];
+    __shared__ uint32_t s_tile;
+    const uint32_t n_tiles = hdr->n_tiles;
+    int cur = -1;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= n_tiles) break;
+        const uint32_t tw = tiles[tile];
+        const int req = (int)(tw >> 26);
+        const int tx = (int)(tw & 0x1FFFu), ty = (int)((tw >> 13) & 0x1FFFu);
+        if (req != cur) {
+            const uint32_t *src = (const uint32_t *)(descs + req);
+            uint32_t *dst = (uint32_t *)&sA;
+            for (unsigned i = threadIdx.x; i < sizeof(RenderArgs) / 4; i += blockDim.x) dst[i] = src[i];
+            __syncthreads();
+            stage_frame<NV>(sA, s_tf, s_ch, s_runs, s_lv, s_nd);
+            cur = req;
+        }
+        const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+        const int px = tx * 32 + (wv & 3) * 8 + (ln & 7);
+        const int py = ty * 16 + (wv >> 2) * 8 + (ln >> 3);
+        uint32_t st[5] = {0, 0, 0, 0, 0};
+        render_pixel<NV, BPV, false>(sA, px, py, px < sA.W && py < sA.H, s_tf, s_ch, s_runs, s_lv, s_nd, st);
+        if (sA.stats) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                uint32_t v = st[q];
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                if ((threadIdx.x & 63) == 0 && v) atomicAdd(&sA.stats[q], (unsigned long long)v);
+            }
+        }
+        __syncthreads();  // sA / LDS tables and s_tile are reused by the next tile
+    }
+}
+
+__global__ void k_serve_reset(uint32_t *queue) {
+    if (threadIdx.x == 0) *queue = 0;
+}
+
+ro_status build_render_args(ro_octree *tr, const ro_frame_desc *fd, float *rgba, RenderArgs &A);
+
+}  // namespace ro
+
+using namespace ro;
+
+struct ro_server {
+    ro_octree *tree;
+    uint32_t max_req, max_tiles;
+    int ncu;
+    uint8_t *host;        // pinned host memory: 2 halves
+    uint8_t *dev;         // caller-owned device buffer: 2 halves + 2 queue counters
+    size_t half;          // bytes per half
+    int cur;              // half the next prepare writes
+    int ready;            // half prepared and not yet submitted (-1: none)
+    int nv[2];            // channel template of each half's batch
+    uint64_t ticket[2];   // last ticket submitted from each half
+    uint64_t next_ticket;
+    hipStream_t stream[2];
+    hipEvent_t ev[2];
+    hipGraph_t graph[2];
+    hipGraphExec_t exec[2];
+};
+
+static size_t serve_half_bytes(uint32_t max_req, uint32_t max_tiles) {
+    size_t b = sizeof(ServeHeader) + (size_t)max_req * sizeof(RenderArgs) + 4 * (size_t)max_tiles;
+    return (b + 4095) / 4096 * 4096;
+}
+
+static inline uint32_t *serve_queue(const ro_server *s, int h) {
+    return (uint32_t *)(s->dev + 2 * s->half + 256 * (size_t)h);
+}
+
+template <int NV, int BPV>
+static hipError_t serve_attr() {
+    return hipFuncSetAttribute((const void *)k_serve<NV, BPV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(sizeof(float4) * 256 * NV));
+}
+
+template <int NV, int BPV>
+static void serve_launch_t(const ro_server *s, int h, hipStream_t st) {
+    const uint8_t *d = s->dev + (size_t)h * s->half;
+    const ServeHeader *dh = (const ServeHeader *)d;
+    const RenderArgs *dd = (const RenderArgs *)(d + sizeof(ServeHeader));
+    const uint32_t *dt = (const uint32_t *)(d + sizeof(ServeHeader) + (size_t)s->max_req * sizeof(RenderArgs));
+    uint32_t *q = serve_queue(s, h);
+    hipLaunchKernelGGL(k_serve_reset, dim3(1), dim3(64), 0, st, q);
+    hipLaunchKernelGGL((k_serve<NV, BPV>), dim3(2 * s->ncu), dim3(512), sizeof(float4) * 256 * NV, st, dh, dd, dt,
+                       q);
+}
+
+// Device work of one submission from half h: copy, queue reset, kernel.
+static hipError_t serve_enqueue(const ro_server *s, int h, hipStream_t st) {
+    hipError_t e = hipMemcpyAsync(s->dev + (size_t)h * s->half, s->host + (size_t)h * s->half, s->half,
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    const bool b1 = s->tree->cache->vol->g.bpv == 1;
+    switch (s->nv[h]) {
+        case 4: b1 ? serve_launch_t<4, 1>(s, h, st) : serve_launch_t<4, 2>(s, h, st); break;
+        case 8: b1 ? serve_launch_t<8, 1>(s, h, st) : serve_launch_t<8, 2>(s, h, st); break;
+        default: b1 ? serve_launch_t<16, 1>(s, h, st) : serve_launch_t<16, 2>(s, h, st); break;
+    }
+    return hipGetLastError();
+}
+
+extern "C" ro_status ro_serve_query(uint32_t max_requests, uint32_t max_tiles, size_t *device_bytes) {
+    RO_CHECK(device_bytes, RO_E_ARG, "null argument");
+    *device_bytes = 2 * serve_half_bytes(max_requests, max_tiles) + 512;
+    return RO_OK;
+}
+
+extern "C" void ro_serve_destroy(ro_server *s) {
+    if (!s) return;
+    for (int h = 0; h < 2; ++h) {
+        if (s->stream[h]) (void)hipStreamSynchronize(s->stream[h]);
+        if (s->exec[h]) (void)hipGraphExecDestroy(s->exec[h]);
+        if (s->graph[h]) (void)hipGraphDestroy(s->graph[h]);
+        if (s->ev[h]) (void)hipEventDestroy(s->ev[h]);
+        if (s->stream[h]) (void)hipStreamDestroy(s->stream[h]);
+    }
+    if (s->host) (void)hipHostFree(s->host);
+    delete s;
+}
+
+extern "C" ro_status ro_serve_create(ro_octree *t, uint32_t max_requests, uint32_t max_tiles, void *device_buf,
+                                     ro_server **out) {
+    RO_CHECK(t && device_buf && out, RO_E_ARG, "null argument");
+    RO_CHECK(((uintptr_t)device_buf & 255u) == 0, RO_E_ARG, "device buffer must be 256-byte aligned");
+    RO_CHECK(max_requests >= 1 && max_requests <= 64, RO_E_ARG, "max_requests not in 1..64");
+    RO_CHECK(max_tiles >= 1 && max_tiles <= (1u << 24), RO_E_ARG, "max_tiles not in 1..2^24");
+    ro_server *s = new (std::nothrow) ro_server();
+    RO_CHECK(s, RO_E_NOMEM, "out of host memory");
+    s->tree = t;
+    s->max_req = max_requests;
+    s->max_tiles = max_tiles;
+    s->half = serve_half_bytes(max_requests, max_tiles);
+    s->dev = (uint8_t *)device_buf;
+    s->ready = -1;
+    s->nv[0] = s->nv[1] = 16;
+    s->next_ticket = 1;
+    hipError_t e = hipSuccess;
+    int dev = 0;
+    void *h = nullptr;
+    const char *what = "server set-up";
+    do {
+        if ((e = hipGetDevice(&dev)) != hipSuccess) break;
+        if ((e = hipDeviceGetAttribute(&s->ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) break;
+        if ((e = hipHostMalloc(&h, 2 * s->half, hipHostMallocDefault)) != hipSuccess) {
+            what = "hipHostMalloc";
+            break;
+        }
+        s->host = (uint8_t *)h;
+        memset(h, 0, 2 * s->half);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+            e = hipStreamCreateWithFlags(&s->stream[k], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) break;
+        // dynamic LDS limits are set here: attribute calls are not made
+        // while a stream is being captured
+        if ((e = serve_attr<4, 1>()) != hipSuccess || (e = serve_attr<4, 2>()) != hipSuccess ||
+            (e = serve_attr<8, 1>()) != hipSuccess || (e = serve_attr<8, 2>()) != hipSuccess ||
+            (e = serve_attr<16, 1>()) != hipSuccess || (e = serve_attr<16, 2>()) != hipSuccess)
+            break;
+    } while (0);
+    if (e != hipSuccess) {
+        ro_serve_destroy(s);
+        return hip_fail(e, what);
+    }
+    *out = s;
+    return RO_OK;
+}
+
+extern "C" ro_status ro_serve_prepare(ro_server *s, uint32_t n, const ro_frame_desc *fds, float *const *rgba,
+                                      int32_t full_channels) {
+    RO_CHECK(s && fds && rgba && n >= 1, RO_E_ARG, "null argument");
+    RO_CHECK(n <= s->max_req, RO_E_CAPACITY, "%u requests exceed the server's %u", n, s->max_req);
+    RO_CHECK(s->ready < 0, RO_E_STATE, "a prepared batch has not been submitted");
+    uint32_t nt = 0;
+    int maxvis = 1;
+    for (uint32_t r = 0; r < n; ++r) {
+        ro_status vs = validate_frame(s->tree, &fds[r], rgba[r]);
+        if (vs) return vs;
+        RO_CHECK(!(fds[r].flags & RO_RENDER_AOV), RO_E_ARG, "AOV output is not served");
+        RO_CHECK(fds[r].width <= 8192 * 32 && fds[r].height <= 8192 * 16, RO_E_ARG, "viewport too large");
+        const uint32_t tw = (uint32_t)(fds[r].width + 31) / 32, th = (uint32_t)(fds[r].height + 15) / 16;
+        RO_CHECK(tw * th <= s->max_tiles - nt, RO_E_CAPACITY, "batch exceeds %u tiles", s->max_tiles);
+        nt += tw * th;
+        maxvis = fds[r].n_vis > maxvis ? fds[r].n_vis : maxvis;
+    }
+    // the half being written was submitted two batches ago: wait for it
+    const int h = s->cur;
+    RO_HIP(hipEventSynchronize(s->ev[h]));
+    uint8_t *base = s->host + (size_t)h * s->half;
+    ServeHeader *hh = (ServeHeader *)base;
+    RenderArgs *hd = (RenderArgs *)(base + sizeof(ServeHeader));
+    uint32_t *ht = (uint32_t *)(base + sizeof(ServeHeader) + (size_t)s->max_req * sizeof(RenderArgs));
+    nt = 0;
+    for (uint32_t r = 0; r < n; ++r) {
+        RenderArgs A;
+        ro_status st = build_render_args(s->tree, &fds[r], rgba[r], A);
+        if (st) {
+            hh->n_tiles = 0;
+            return st;
+        }
+        memcpy(&hd[r], &A, sizeof(A));
+        // a request's tiles are consecutive: a workgroup re-stages its LDS
+        // tables only when it crosses into the next request
+        const uint32_t tw = (uint32_t)(fds[r].width + 31) / 32, th = (uint32_t)(fds[r].height + 15) / 16;
+        for (uint32_t y = 0; y < th; ++y)
+            for (uint32_t x = 0; x < tw; ++x) ht[nt++] = (r << 26) | (y << 13) | x;
+    }
+    hh->n_tiles = nt;
+    hh->n_req = n;
+    s->nv[h] = full_channels ? 16 : (maxvis <= 4 ? 4 : (maxvis <= 8 ? 8 : 16));
+    s->ready = h;
+    return RO_OK;
+}
+
+extern "C" ro_status ro_serve_submit(ro_server *s, uint32_t flags, uint64_t *ticket) {
+    RO_CHECK(s, RO_E_ARG, "null argument");
+    RO_CHECK(s->ready >= 0, RO_E_STATE, "no prepared batch");
+    const int h = s->ready;
+    hipStream_t st = s->stream[h];
+    if (flags & RO_SERVE_GRAPH) {
+        RO_CHECK(s->nv[h] == 16, RO_E_ARG, "graph submission needs a batch prepared with full_channels");
+        if (!s->exec[h]) {
+            RO_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            hipError_t e = serve_enqueue(s, h, st);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(st, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(e != hipSuccess ? e : e2, "graph capture");
+            }
+            e = hipGraphInstantiate(&s->exec[h], g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                s->exec[h] = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            s->graph[h] = g;
+        }
+        RO_HIP(hipGraphLaunch(s->exec[h], st));
+    } else {
+        RO_HIP(serve_enqueue(s, h, st));
+    }
+    RO_HIP(hipEventRecord(s->ev[h], st));
+    s->ticket[h] = s->next_ticket++;
+    if (ticket) *ticket = s->ticket[h];
+    s->cur = h ^ 1;
+    s->ready = -1;
+    return RO_OK;
+}
+
+static ro_status serve_ticket_half(const ro_server *s, uint64_t ticket, int *h) {
+    RO_CHECK(ticket >= 1 && ticket < s->next_ticket, RO_E_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    *h = -1;  // older than both halves' last submissions: finished
+    for (int k = 0; k < 2; ++k)
+        if (s->ticket[k] == ticket) *h = k;
+    return RO_OK;
+}
+
+extern "C" ro_status ro_serve_poll(ro_server *s, uint64_t ticket, int32_t *done) {
+    RO_CHECK(s && done, RO_E_ARG, "null argument");
+    int h;
+    ro_status st = serve_ticket_half(s, ticket, &h);
+    if (st) return st;
+    if (h < 0) {
+        *done = 1;
+        return RO_OK;
+    }
+    hipError_t e = hipEventQuery(s->ev[h]);
+    if (e == hipErrorNotReady) {
+        *done = 0;
+        return RO_OK;
+    }
+    RO_HIP(e);
+    *done = 1;
+    return RO_OK;
+}
+
+extern "C" ro_status ro_serve_wait(ro_server *s, uint64_t ticket) {
+    RO_CHECK(s, RO_E_ARG, "null argument");
+    int h;
+    ro_status st = serve_ticket_half(s, ticket, &h);
+    if (st) return st;
+    if (h >= 0) RO_HIP(hipEventSynchronize(s->ev[h]));
+    return RO_OK;
+}
+
+extern "C" ro_status ro_serve_launch(ro_server *s, uint32_t n, const ro_frame_desc *fds, float *const *rgba,
+                                     uint64_t *ticket) {
+    ro_status st = ro_serve_prepare(s, n, fds, rgba, 0);
+    if (st) return st;
+    return ro_serve_submit(s, 0, ticket);
+}

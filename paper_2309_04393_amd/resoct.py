@@ -14,7 +14,8 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_lib", "libresoct.so")
+# RESOCT_LIB selects another build of the same library (same ABI)
+LIB_PATH = os.environ.get("RESOCT_LIB", os.path.join(HERE, "_lib", "libresoct.so"))
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
@@ -470,3 +471,61 @@ class PrefetchRows:
                                      _stream(stream)), "ro_pf_candidates")
         k = min(cap, n.value)
         return ids[:k], pr[:k]
+
+
+SERVE_GRAPH = 1
+_sig("ro_serve_query", c_i32, [c_u32, c_u32, _P(c_sz)])
+_sig("ro_serve_create", c_i32, [c_vp, c_u32, c_u32, c_vp, _P(c_vp)])
+_sig("ro_serve_destroy", None, [c_vp])
+_sig("ro_serve_prepare", c_i32, [c_vp, c_u32, c_vp, c_vp, c_i32])
+_sig("ro_serve_submit", c_i32, [c_vp, c_u32, _P(c_u64)])
+_sig("ro_serve_poll", c_i32, [c_vp, c_u64, _P(c_i32)])
+_sig("ro_serve_wait", c_i32, [c_vp, c_u64])
+
+
+class Server:
+    """Batched multi-request rendering over one octree (persistent tile-queue
+    kernel, two alternating batch halves with their own streams)."""
+
+    def __init__(self, tree: Octree, max_requests=64, max_tiles=1 << 16, device="cuda"):
+        nb = c_sz()
+        _check(_lib.ro_serve_query(max_requests, max_tiles, ctypes.byref(nb)), "ro_serve_query")
+        self.buf = _alloc(nb.value, device)
+        h = c_vp()
+        _check(_lib.ro_serve_create(tree.h, max_requests, max_tiles, _dev_ptr(self.buf), ctypes.byref(h)),
+               "ro_serve_create")
+        self.h = h
+        self.tree = tree
+        self.max_requests, self.max_tiles = max_requests, max_tiles
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.ro_serve_destroy(self.h)
+            self.h = None
+
+    def prepare(self, fds, outs, full_channels=False):
+        n = len(fds)
+        assert n == len(outs) and n >= 1
+        for fd, o in zip(fds, outs):
+            assert o.dtype == torch.float32 and o.is_contiguous() and o.numel() >= 4 * fd.width * fd.height
+        arr = (FrameDesc * n)(*fds)
+        ptrs = (c_vp * n)(*[o.data_ptr() for o in outs])
+        _check(_lib.ro_serve_prepare(self.h, n, ctypes.cast(arr, c_vp), ctypes.cast(ptrs, c_vp),
+                                     1 if full_channels else 0), "ro_serve_prepare")
+
+    def submit(self, graph=False) -> int:
+        t = c_u64()
+        _check(_lib.ro_serve_submit(self.h, SERVE_GRAPH if graph else 0, ctypes.byref(t)), "ro_serve_submit")
+        return int(t.value)
+
+    def launch(self, fds, outs, graph=False) -> int:
+        self.prepare(fds, outs, full_channels=graph)
+        return self.submit(graph)
+
+    def poll(self, ticket: int) -> bool:
+        d = c_i32()
+        _check(_lib.ro_serve_poll(self.h, ticket, ctypes.byref(d)), "ro_serve_poll")
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        _check(_lib.ro_serve_wait(self.h, ticket), "ro_serve_wait")
