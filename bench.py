@@ -337,6 +337,68 @@ def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True):
     return out
 
 
+def prefetch_bench(train_seeds=tuple(range(1000, 1010)), eval_seeds=tuple(range(1010, 1015)), n_frames=120,
+                   U=512, lr=1e-3):
+    """Learned prefetcher against plain request-driven streaming on the
+    4-channel 2048 x 2048 x 64 cell volume (2 GiB cache, 1024 x 1024
+    perspective views, upload budget U bricks per frame): the network trains
+    online along the training paths, then both policies run each held-out
+    path from an empty cache."""
+    import torch
+
+    import synth
+    from paper_2309_04393_amd import resoct
+    from paper_2309_04393_amd.pipeline import GpuScene
+    from paper_2309_04393_amd.prefetch import BrickStore, run_path, save_state
+    vol = synth.config2_volume()
+    t = time.perf_counter()
+    scene = GpuScene(vol, 32, (16, 16, 4), 7, 27318, max_batch=U, start_level=2, set_metadata=False)
+    lg = leaf_grid(vol.dims, (16, 16, 4), 7)
+    mx = vol.leaf_max_all((16, 16, 4), lg)
+    for c in range(vol.n_channels):
+        mm = np.zeros((mx.shape[1], 2), np.uint16)
+        mm[:, 1] = mx[c]
+        scene.set_metadata(c, mm)
+    store = BrickStore(scene)
+    empty = save_state(scene)
+    log(f"prefetch scene: {len(store.index)} bricks in the device store ({time.perf_counter() - t:.1f} s)")
+    chans = [dict(ch, hi=vol.n_levels - 1) for ch in channels(vol.n_channels, 2)]
+    W = H = 1024
+    step = 0.5 * min(vol.spacing)
+    net = resoct.Mlp()
+    net.set_weights(synth.mlp_init(7))
+    path = lambda s: synth.random_path(vol.dims, vol.spacing, s, n_frames)
+    t = time.perf_counter()
+    train = []
+    for s in train_seeds:
+        _, sm = run_path(scene, store, path(s), chans, W, H, U, step, "learned", net, empty, lr=lr)
+        train.append(sm)
+        log(f"train path {s}: {sm}")
+    t_train = time.perf_counter() - t
+    ev = []
+    for s in eval_seeds:
+        cams = path(s)
+        _, sp = run_path(scene, store, cams, chans, W, H, U, step, "plain", None, empty)
+        _, sl = run_path(scene, store, cams, chans, W, H, U, step, "learned", net, empty, lr=lr)
+        ev.append({"seed": s, "plain": sp, "learned": sl})
+        log(f"eval path {s}: plain {sp}")
+        log(f"eval path {s}: learned {sl}")
+
+    def agg(key, pol):
+        v = [e[pol][key] for e in ev]
+        return None if any(x is None for x in v) else float(np.mean(v))
+
+    out = {"workload": "4ch-2048x2048x64-u16 cells, 2 GiB cache, 1024x1024 perspective, random paths",
+           "frames_per_path": n_frames, "upload_budget": U, "train_paths": list(train_seeds),
+           "eval_paths": list(eval_seeds), "train_s": t_train,
+           "summary": {pol: {k: agg(k, pol) for k in ("first_below_1pct", "stays_below_1pct", "mean_missing",
+                                                       "bytes_streamed")} for pol in ("plain", "learned")},
+           "paths": ev}
+    del store, scene
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,6 +411,8 @@ def main():
                     help="seconds of the serving measurement after the frame measurement (0: skip)")
     ap.add_argument("--serve-only", action="store_true", help="only the serving measurement")
     ap.add_argument("--rate", type=float, default=400.0, help="serving arrival rate, requests/s")
+    ap.add_argument("--prefetch-only", action="store_true",
+                    help="only the learned-prefetcher evaluation (10 training, 5 held-out paths)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the measurement, copy a 1 GiB buffer three times (a plain copy kernel of "
                          "known size, to scale hardware byte counters)")
@@ -362,6 +426,9 @@ def main():
     import synth
     from paper_2309_04393_amd.pipeline import GpuScene
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.prefetch_only:
+        print(json.dumps({"prefetch": prefetch_bench()}), flush=True)
+        return
     if args.serve_only:
         print(json.dumps({"serving": serve_bench(args.rate, args.serve)}), flush=True)
         return

@@ -4,6 +4,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -20,22 +21,27 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OUT_DIR, exist_ok=True)
+def build(verbose: bool = False, csrc: str = CSRC, lib: str = LIB) -> str:
+    """Compile every source (in parallel) and link lib."""
+    out_dir = os.path.dirname(lib)
+    os.makedirs(out_dir, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
-        obj = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
-        cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
-               os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        obj = os.path.join(out_dir, src.replace(".hip", ".o"))
+        cmds.append([hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", csrc, "-c",
+                     os.path.join(csrc, src), "-o", obj])
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    if verbose:
+        for c in cmds:
+            print(" ".join(c), flush=True)
+    jobs = max(1, min(len(cmds), os.cpu_count() or 1, int(os.environ.get("MAX_JOBS", "16"))))
+    with ThreadPoolExecutor(jobs) as ex:
+        list(ex.map(subprocess.check_call, cmds))
+    tmp = lib + ".tmp"
     subprocess.check_call([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -126,3 +126,49 @@ def frames_to_converge(log, thr=0.01):
         if r["missing"] < thr:
             return r["frame"]
     return None
+
+
+def first_below(log, thr=0.01, hold=1):
+    """First frame from which the missing-sample fraction stays below thr
+    for `hold` frames (None if never)."""
+    for i in range(len(log)):
+        win = log[i:i + hold]
+        if len(win) == hold and all(r["missing"] < thr for r in win):
+            return log[i]["frame"]
+    return None
+
+
+def run_path(scene, store, cams, chans, W, H, U, step, policy, net=None, empty_state=None, lr=1e-3,
+             train=True, lod_bias=1.0, threshold=0.5):
+    """One camera path from an empty cache; returns the loop's per-frame
+    log and a summary."""
+    if empty_state is not None:
+        restore_state(scene, empty_state)
+    loop = StreamingLoop(scene, store, chans, W, H, U, step, policy=policy, net=net, lr=lr,
+                         threshold=threshold, lod_bias=lod_bias, train=train)
+    for f, cam in enumerate(cams, start=1):
+        loop.frame(f, cam)
+    log = loop.log
+    miss = np.array([r["missing"] for r in log])
+    return log, dict(frames=len(log), first_below_1pct=first_below(log, 0.01),
+                     stays_below_1pct=first_below(log, 0.01, hold=5),
+                     mean_missing=float(miss.mean()), bytes_streamed=int(sum(r["bytes"] for r in log)),
+                     uploads=int(sum(r["uploads"] for r in log)), extra=int(sum(r["extra"] for r in log)),
+                     learned_frames=int(sum(1 for r in log if r["learned"])),
+                     precision=loop.precision() if policy == "learned" else None)
+
+
+def save_state(scene):
+    """Device buffers and host mirror of a scene's cache and octree."""
+    dev = {("c", k): v.clone() for k, v in scene.cache.t.items() if k not in ("scratch", "slots")}
+    dev.update({("t", k): v.clone() for k, v in scene.tree.t.items() if k != "scratch"})
+    torch.cuda.synchronize()
+    return dev, scene.cache.save_state()
+
+
+def restore_state(scene, state):
+    dev, host = state
+    for (kind, k), v in dev.items():
+        (scene.cache.t if kind == "c" else scene.tree.t)[k].copy_(v)
+    torch.cuda.synchronize()
+    scene.cache.load_state(host)
