@@ -136,16 +136,13 @@ def restore(scene, snap):
     scene.cache.load_state(host)
 
 
-def cpu_baseline(cfg, scene, cams, chans, f, step, tile):
-    """The oracle on a tile x tile pixel window of frame f, every brick
-    resident (samples read their desired level), level data materialised
-    for the window's rays from the generator."""
+def oracle_window(cfg, cam, W, H, x0, y0, tile, step, chans, need=2):
+    """Oracle inputs for the tile x tile pixel window at (x0, y0) of a W x H
+    frame: the volume description, level data materialised (levels below
+    `need`) over the bounding box of the window's rays, the boxes, leaf
+    metadata and the oracle frame of the window's sub-camera."""
     import oracle
     vol = cfg["vol"]
-    W, H = cfg["W"], cfg["H"]
-    cam = cams[f]
-    x0, y0 = (W - tile) // 2, (H - tile) // 2
-    # bounding box of the tile's rays inside the volume (edge pixels)
     V = oracle.make_volume(vol.dims, vol.spacing, vol.n_channels, 16, cfg["B"], vol.n_levels, cfg["leaf"],
                            cfg["depth"])
     eye = np.array(cam["eye"]) / np.array(vol.spacing)
@@ -173,7 +170,6 @@ def cpu_baseline(cfg, scene, cams, chans, f, step, tile):
     hi = np.clip(np.ceil(hi) + 2, 1, dims).astype(int)
     ldims, lf, _ = oracle.level_info(V)
     levels, boxes = [], np.zeros((vol.n_channels, vol.n_levels, 6), np.int32)
-    need = 2  # levels materialised (the timed frames read levels 0-1)
     per_level = []
     for l in range(vol.n_levels):
         if l >= need:
@@ -195,22 +191,30 @@ def cpu_baseline(cfg, scene, cams, chans, f, step, tile):
                 row.append(np.ascontiguousarray(reg[c]))
                 boxes[c, l] = [a[0], a[1], a[2], n[0], n[1], n[2]]
         levels.append(row)
-    lm = scene_leaf_mm(cfg, V)
+    lm = leaf_mm_all(cfg)
+    fr, keep = oracle.make_frame(sub_camera(cam, W, H, x0, y0, tile), tile, tile, step,
+                                 [dict(ch, hi=vol.n_levels - 1) for ch in chans], term_margin=1e-6)
+    return V, levels, boxes, lm, fr
+
+
+def cpu_baseline(cfg, cams, chans, f, step, tile):
+    """The oracle on a tile x tile pixel window at the centre of frame f,
+    every brick resident (samples read their desired level), level data
+    materialised for the window's rays from the generator."""
+    import oracle
+    W, H = cfg["W"], cfg["H"]
+    x0, y0 = (W - tile) // 2, (H - tile) // 2
+    V, levels, boxes, lm, fr = oracle_window(cfg, cams[f], W, H, x0, y0, tile, step, chans)
     res = np.arange(oracle.brick_count(V), dtype=np.int32)
-    fr, keep = oracle.make_frame(cam, W, H, step, [dict(ch, hi=vol.n_levels - 1) for ch in chans])
-    # restrict to the tile: render rows y0..y0+tile of a frame cropped to the tile's columns by
-    # shifting the camera window: use the row band and ignore columns outside the tile
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    fr2, keep2 = oracle.make_frame(sub_camera(cam, W, H, x0, y0, tile), tile, tile, step,
-                                   [dict(ch, hi=vol.n_levels - 1) for ch in chans])
     t = time.perf_counter()
-    r = oracle.render(V, levels, res, lm, fr2, 1, n_threads=threads, boxes=boxes)
+    r = oracle.render(V, levels, res, lm, fr, 1, n_threads=threads, boxes=boxes)
     dt = time.perf_counter() - t
     assert not np.isnan(r["rgba"]).any(), "oracle sampled outside the materialised window"
     s = r["stats"]["samples"]
     return dict(value=s / dt, unit="samples/s", cores=threads, kind="oracle",
                 sample=f"{tile}x{tile}-pixel window at the centre of timed frame {f}, all bricks resident, "
-                       f"{s} ray samples x {len(chans)} channels in {dt:.1f} s"), r
+                       f"{s} ray samples x {len(chans)} channels in {dt:.1f} s"), r, (x0, y0)
 
 
 def sub_camera(cam, W, H, x0, y0, n):
@@ -249,10 +253,6 @@ def leaf_mm_all(cfg):
         mm[:, :, 1] = mx
         _LM[key] = mm
     return _LM[key]
-
-
-def scene_leaf_mm(cfg, V=None):
-    return leaf_mm_all(cfg)
 
 
 def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True):
@@ -541,9 +541,20 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 1 << 30
     if not args.no_cpu_baseline:
+        # the oracle's window of the last timed frame, which read every sample
+        # from its desired level (no missing samples), against the GPU image
+        fl_last = f0 + K - 1
+        img = fl.out[: cfg["W"] * cfg["H"] * 4].view(cfg["H"], cfg["W"], 4).cpu().numpy().astype(np.float64)
         try:
-            cb, _ = cpu_baseline(cfg, scene, cams, chans, f0, step, args.tile)
+            cb, r, (x0, y0) = cpu_baseline(cfg, cams, chans, fl_last, step, args.tile)
             out["cpu_baseline"] = cb
+            win = img[y0:y0 + args.tile, x0:x0 + args.tile]
+            ok = r["amb_pix"] == 0
+            d = np.abs(win - r["rgba"])[ok]
+            out["parity"] = {"window": [x0, y0, args.tile, args.tile], "frame": fl_last,
+                             "missing_samples_in_frame": int(stats_a[-1][2]),
+                             "max_abs": d.max(axis=0).tolist(), "mean_abs": d.mean(axis=0).tolist(),
+                             "ambiguous_frac": float(1.0 - ok.mean())}
         except Exception as e:  # reported, not fatal
             out["cpu_baseline"] = {"error": repr(e)}
     if args.serve > 0:

@@ -364,7 +364,7 @@ ro_status ro_pf_candidates(ro_prefetch *p, const float *z_dev, float threshold, 
 /* Batched rendering for a serving loop (an addition to the paper's method):
  * one persistent kernel renders up to 64 frame requests of different
  * viewports, channel subsets, transfer functions and cameras over the shared
- * cache and octree; its workgroups pop 32 x 16-pixel tiles from a device
+ * cache and octree; its workgroups pop 32 x 32-pixel tiles from a device
  * queue.  Each pixel runs the same code as ro_render, so a request's image is
  * the same alone and in any batch.
  *

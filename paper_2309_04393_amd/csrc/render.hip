@@ -1,7 +1,7 @@
 // Ray-guided mixed-resolution multi-channel ray casting over the residency
 // octree (Sec. 6.1, Alg. 1; Sec. 6.2; Sec. 6 implementation notes).
 //
-// One lane per pixel; a 512-lane workgroup covers a 32 x 16 pixel tile.
+// One lane per pixel; a 1024-lane workgroup covers a 32 x 32 pixel tile.
 // Sample positions and every integer decision derived from them (box, leaf,
 // brick, level) are computed in FP64; interpolation, transfer functions and
 // the channel mix in FP32; the compositing state in FP64.  Per lane, the
@@ -21,9 +21,16 @@
 
 namespace ro {
 
+// 1024-lane workgroups (16 waves of 8 x 8 pixels, a 32 x 32 pixel tile):
+// one workgroup per CU holds one copy of the frame's LDS tables plus the
+// per-lane slot words, at 4 waves per SIMD.
+constexpr int kWaveW = 8, kWaveH = 8;
+constexpr int kWavesX = 4, kWavesY = kRenderLanes / 256;
+constexpr int kTileW = kWavesX * kWaveW, kTileH = kWavesY * kWaveH;
+
 template <int NV, int BPV, bool AOV>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_render(const RenderArgs A) {
-    extern __shared__ float4 s_tf[];  // [nvis][256]
+__global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(4))) k_render(const RenderArgs A) {
+    extern __shared__ float4 s_tf[];  // [NV][256] tables, then [NV][kRenderLanes] slot words
     __shared__ ChanLds s_ch[NV];
     __shared__ uint32_t s_runs[NV * kMaxRuns];
     __shared__ LevLds s_lv[kMaxL];
@@ -31,12 +38,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
 
     stage_frame<NV>(A, s_tf, s_ch, s_runs, s_lv, s_nd);
 
-    // 32 x 16 pixels per workgroup, 8 x 8 pixels per wave
+    const int tx = blockIdx.x, ty = blockIdx.y;
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    const int px = blockIdx.x * 32 + (wv & 3) * 8 + (ln & 7);
-    const int py = blockIdx.y * 16 + (wv >> 2) * 8 + (ln >> 3);
+    const int px = tx * kTileW + (wv % kWavesX) * kWaveW + (ln % kWaveW);
+    const int py = ty * kTileH + (wv / kWavesX) * kWaveH + (ln / kWaveW);
     uint32_t st[5] = {0, 0, 0, 0, 0};
-    render_pixel<NV, BPV, AOV>(A, px, py, px < A.W && py < A.H, s_tf, s_ch, s_runs, s_lv, s_nd, st);
+    const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
+    render_pixel<NV, BPV, AOV>(A, px, py, px < A.W && py < A.H, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
     if (A.stats) {
         // every lane of the workgroup is here: reduce over the wave, one atomic per wave
 #pragma unroll
@@ -50,26 +58,27 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
 }
 
 template <int NV, int BPV, bool AOV>
-static hipError_t launch_one(const RenderArgs &A, dim3 grid, size_t lds, hipStream_t s) {
+static hipError_t launch_one(const RenderArgs &A, dim3 grid, hipStream_t s) {
+    const size_t lds = render_lds_bytes(NV);
     hipError_t e = hipFuncSetAttribute((const void *)k_render<NV, BPV, AOV>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_render<NV, BPV, AOV>), grid, dim3(512), lds, s, A);
+    hipLaunchKernelGGL((k_render<NV, BPV, AOV>), grid, dim3(kRenderLanes), lds, s, A);
     return hipGetLastError();
 }
 
 template <int NV, int BPV>
-static hipError_t launch_nv(const RenderArgs &A, bool aov, dim3 grid, size_t lds, hipStream_t s) {
-    return aov ? launch_one<NV, BPV, true>(A, grid, lds, s) : launch_one<NV, BPV, false>(A, grid, lds, s);
+static hipError_t launch_nv(const RenderArgs &A, bool aov, dim3 grid, hipStream_t s) {
+    return aov ? launch_one<NV, BPV, true>(A, grid, s) : launch_one<NV, BPV, false>(A, grid, s);
 }
 
 template <int BPV>
-static hipError_t launch_bpv(const RenderArgs &A, bool aov, dim3 grid, size_t lds, hipStream_t s) {
-    if (A.nvis <= 1) return launch_nv<1, BPV>(A, aov, grid, lds, s);
-    if (A.nvis <= 2) return launch_nv<2, BPV>(A, aov, grid, lds, s);
-    if (A.nvis <= 4) return launch_nv<4, BPV>(A, aov, grid, lds, s);
-    if (A.nvis <= 8) return launch_nv<8, BPV>(A, aov, grid, lds, s);
-    return launch_nv<16, BPV>(A, aov, grid, lds, s);
+static hipError_t launch_bpv(const RenderArgs &A, bool aov, dim3 grid, hipStream_t s) {
+    if (A.nvis <= 1) return launch_nv<1, BPV>(A, aov, grid, s);
+    if (A.nvis <= 2) return launch_nv<2, BPV>(A, aov, grid, s);
+    if (A.nvis <= 4) return launch_nv<4, BPV>(A, aov, grid, s);
+    if (A.nvis <= 8) return launch_nv<8, BPV>(A, aov, grid, s);
+    return launch_nv<16, BPV>(A, aov, grid, s);
 }
 
 // Kernel arguments of one frame (validated by the caller).
@@ -164,10 +173,9 @@ ro_status render_device(ro_octree *tr, const ro_frame_desc *fd, float *rgba, hip
     RenderArgs A;
     ro_status st = build_render_args(tr, fd, rgba, A);
     if (st) return st;
-    dim3 grid((fd->width + 31) / 32, (fd->height + 15) / 16);
-    const size_t lds = sizeof(float4) * 256 * (size_t)fd->n_vis;
+    dim3 grid((fd->width + kTileW - 1) / kTileW, (fd->height + kTileH - 1) / kTileH);
     const bool aov = (fd->flags & RO_RENDER_AOV) != 0;
-    RO_HIP(g.bpv == 1 ? launch_bpv<1>(A, aov, grid, lds, s) : launch_bpv<2>(A, aov, grid, lds, s));
+    RO_HIP(g.bpv == 1 ? launch_bpv<1>(A, aov, grid, s) : launch_bpv<2>(A, aov, grid, s));
     return RO_OK;
 }
 

@@ -96,10 +96,29 @@ __device__ __forceinline__ bool range_empty(uint32_t mm, const uint32_t *runs, i
     return false;
 }
 
+// Two horizontally adjacent voxels (x, x + 1) in one load; the voxel grid
+// is only 1- or 2-byte aligned, which global loads allow on this target.
 template <int BPV>
-__device__ __forceinline__ float voxel(const uint8_t *p, uint32_t idx) {
-    if (BPV == 1) return (float)p[idx];
-    return (float)((const uint16_t *)p)[idx];
+__device__ __forceinline__ uint32_t vpair(const uint8_t *p) {
+    if (BPV == 1) {
+        uint16_t v;
+        __builtin_memcpy(&v, p, 2);
+        return v;
+    }
+    uint32_t v;
+    __builtin_memcpy(&v, p, 4);
+    return v;
+}
+
+template <int BPV>
+__device__ __forceinline__ void unpack(uint32_t w, float v[2]) {
+    if (BPV == 1) {
+        v[0] = (float)(w & 0xFFu);
+        v[1] = (float)((w >> 8) & 0xFFu);
+    } else {
+        v[0] = (float)(w & 0xFFFFu);
+        v[1] = (float)(w >> 16);
+    }
 }
 
 __device__ __forceinline__ uint32_t brick_dense(const LevLds &lv, uint32_t c, uint32_t per_channel, int bx,
@@ -111,15 +130,34 @@ __device__ __forceinline__ uint32_t node_at(const NodeLds &nd, int x, int y, int
     return nd.noff + ((((uint32_t)z << field(nd.nlg, 1)) + (uint32_t)y) << field(nd.nlg, 0)) + (uint32_t)x;
 }
 
+// Lanes per workgroup of the render and serve kernels.
+constexpr int kRenderLanes = 1024;
+
+// Dynamic LDS of a workgroup: NV transfer-function tables, then one slot
+// word per lane and visible channel.
+__host__ __device__ constexpr size_t render_lds_bytes(int nv) {
+    return (size_t)nv * 256 * 16 + (size_t)nv * kRenderLanes * 4;
+}
+
+// Slot of each visible channel for a lane's current visit, kept in LDS (one
+// word per lane and channel, lane-minor so a wave's accesses are
+// conflict-free) rather than in registers.
+struct LdsSlots {
+    uint32_t *p;      // this lane's first word
+    uint32_t stride;  // lanes in the workgroup
+    __device__ __forceinline__ uint32_t &operator[](int j) { return p[(uint32_t)j * stride]; }
+};
+
 template <int NV, int BPV, bool AOV>
 __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, const int py, const bool valid,
                                              const float4 *s_tf,
                                              const ChanLds *s_ch, const uint32_t *s_runs, const LevLds *s_lv,
-                                             const NodeLds *s_nd, uint32_t stats[5]) {
+                                             const NodeLds *s_nd, uint32_t stats[5], LdsSlots slot) {
     const int nvis = A.nvis;
     const int D = A.depth;
     const int L = A.L;
     const int m = A.m;
+    constexpr int kGroup = NV < 4 ? NV : 4;  // channels whose gathers are in flight together
 
     // ---- ray in L0 voxel units
     double o[3], d[3];
@@ -187,12 +225,11 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
     int cur_lod = -1, lod = 0;
     while (lod + 1 < L && (unsigned long long)k >= s_lv[lod + 1].K) ++lod;
     uint32_t emask = 0, missmask = 0;
-    uint32_t slot[NV];
     uint64_t lvpack = 0;
     uint32_t nvisit = 0;
     uint32_t st_samples = 0, st_reads = 0, st_miss = 0, st_visits = 0, st_nonempty = 0;
     const uint32_t vismask = (nvis >= 32) ? 0xFFFFFFFFu : ((1u << nvis) - 1u);
-    int lc[3] = {0, 0, 0};  // L0 origin of the visit's leaf
+    int lc[3] = {-1, -1, -1};  // L0 origin of the last visited leaf (none yet)
 #pragma unroll
     for (int j = 0; j < NV; ++j) slot[j] = kInvalid;
     const int s0 = A.start_level;
@@ -257,18 +294,42 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
         if (leaf != cur_leaf || lod != cur_lod) {
             flush();
             if (leaf != cur_leaf) {
-                // descend from the start level; skip the first node that is
-                // empty for every visible channel (the leaf included)
+                // Descend from the start level and skip the first node that
+                // is empty for every visible channel (the leaf included).
+                // Every ancestor of a visited leaf is non-empty, so levels
+                // whose node also holds the last visited leaf are known
+                // non-empty and the test starts below them (the same node
+                // is skipped either way).
+                int d0 = noskip ? D : s0;
+                if (lc[0] >= 0 && !noskip) {
+                    while (d0 < D) {
+                        const uint32_t sh = s_nd[d0].nsh;
+                        if (((iu[0] ^ lc[0]) >> field(sh, 0)) | ((iu[1] ^ lc[1]) >> field(sh, 1)) |
+                            ((iu[2] ^ lc[2]) >> field(sh, 2)))
+                            break;
+                        ++d0;
+                    }
+                }
                 bool skipped = false;
-                for (int dl = noskip ? D : s0; dl <= D; ++dl) {
+                for (int dl = d0; dl <= D; ++dl) {
                     const NodeLds nd = s_nd[dl];
                     const uint32_t node = node_at(nd, iu[0] >> field(nd.nsh, 0), iu[1] >> field(nd.nsh, 1),
                                                   iu[2] >> field(nd.nsh, 2));
+                    // the node's metadata, kGroup channels per batch of loads
                     uint32_t em = 0;
-                    for (int j = 0; j < nvis; ++j) {
-                        const ChanLds ch = s_ch[j];
-                        if (range_empty(A.meta[(size_t)node * m + ch.c], s_runs + j * kMaxRuns, ch.nruns))
-                            em |= 1u << j;
+                    const uint32_t *nm = A.meta + (size_t)node * m;
+#pragma unroll
+                    for (int g = 0; g < NV; g += kGroup) {
+                        if (g >= nvis) break;
+                        uint32_t mm[kGroup];
+#pragma unroll
+                        for (int jj = 0; jj < kGroup; ++jj) mm[jj] = g + jj < nvis ? nm[s_ch[g + jj].c] : 0u;
+#pragma unroll
+                        for (int jj = 0; jj < kGroup; ++jj) {
+                            const int j = g + jj;
+                            if (j < nvis && range_empty(mm[jj], s_runs + j * kMaxRuns, s_ch[j].nruns)) em |= 1u << j;
+                        }
+                        asm volatile("" ::: "memory");
                     }
                     if (dl == D) emask = em;
                     if (em == (1u << nvis) - 1u && !noskip) {
@@ -300,26 +361,46 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
             ++st_visits;
             missmask = 0;
             lvpack = 0;
+            // residency masks of the leaf, then the page-table entries of the
+            // chosen bricks, kGroup channels per batch of loads
+            const uint16_t *lm = A.mask + (size_t)leaf * m;
 #pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                uint32_t ns = kInvalid;
-                if (j < nvis && !((emask >> j) & 1u)) {
-                    const ChanLds ch = s_ch[j];
-                    const int ls = min(max(lod, ch.lo), ch.hi);
-                    const uint32_t mk = (uint32_t)A.mask[(size_t)leaf * m + ch.c] >> ls;
-                    if (!(mk & 1u)) missmask |= 1u << j;
-                    if (mk) {
-                        const int lu = ls + __builtin_ctz(mk);
-                        const LevLds lv = s_lv[lu];
-                        ns = A.pt[brick_dense(lv, (uint32_t)ch.c, A.per_channel, iu[0] >> field(lv.sh, 0),
-                                              iu[1] >> field(lv.sh, 1), iu[2] >> field(lv.sh, 2))];
-                        if (ns != kInvalid) {
+            for (int g = 0; g < NV; g += kGroup) {
+                if (g >= nvis) break;
+                uint32_t mk[kGroup];
+#pragma unroll
+                for (int jj = 0; jj < kGroup; ++jj) {
+                    const int j = g + jj;
+                    mk[jj] = (j < nvis && !((emask >> j) & 1u)) ? (uint32_t)lm[s_ch[j].c] : 0u;
+                }
+#pragma unroll
+                for (int jj = 0; jj < kGroup; ++jj) {
+                    const int j = g + jj;
+                    uint32_t ns = kInvalid;
+                    if (j < nvis && !((emask >> j) & 1u)) {
+                        const ChanLds ch = s_ch[j];
+                        const int ls = min(max(lod, ch.lo), ch.hi);
+                        const uint32_t mj = mk[jj] >> ls;
+                        if (!(mj & 1u)) missmask |= 1u << j;
+                        if (mj) {
+                            const int lu = ls + __builtin_ctz(mj);
+                            const LevLds lv = s_lv[lu];
+                            ns = A.pt[brick_dense(lv, (uint32_t)ch.c, A.per_channel, iu[0] >> field(lv.sh, 0),
+                                                  iu[1] >> field(lv.sh, 1), iu[2] >> field(lv.sh, 2))];
                             lvpack |= (uint64_t)lu << (4 * j);
-                            if (ns != slot[j]) A.stamp[ns] = A.frame;
                         }
                     }
+                    mk[jj] = ns;
                 }
-                slot[j] = ns;
+#pragma unroll
+                for (int jj = 0; jj < kGroup; ++jj) {
+                    const int j = g + jj;
+                    if (j >= nvis) break;
+                    const uint32_t ns = mk[jj];
+                    if (ns == kInvalid) lvpack &= ~((uint64_t)15u << (4 * j));
+                    else if (ns != slot[j]) A.stamp[ns] = A.frame;
+                    slot[j] = ns;
+                }
                 asm volatile("" ::: "memory");
             }
         }
@@ -327,37 +408,75 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
         ++st_samples;
         st_nonempty += __popc(vismask & ~emask);
         // ---- sample every visible channel
+        // In-brick coordinates depend only on the level a channel samples
+        // (bricks of one level share their grid), so they are computed once
+        // per distinct level of the sample.  Channels are gathered in groups
+        // of kGroup: the group's loads are all issued before any of them is
+        // used, and two horizontally adjacent voxels come in one load.
         float prod = 1.0f, sa = 0.0f, sr = 0.0f, sg = 0.0f, sbl = 0.0f;
+        int lprev = -1;
+        uint32_t idx = 0;
+        float fr0 = 0.0f, fr1 = 0.0f, fr2 = 0.0f;
+        const uint32_t E = (uint32_t)A.E;
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            if (j < nvis && slot[j] != kInvalid) {
+        for (int g = 0; g < NV; g += kGroup) {
+            if (g >= nvis) break;
+            uint32_t w[kGroup][4];
+            float fq[kGroup][3];
+            bool ok[kGroup];
+#pragma unroll
+            for (int jj = 0; jj < kGroup; ++jj) {
+                const int j = g + jj;
+                ok[jj] = j < nvis && slot[j] != kInvalid;
                 const int lu = (int)((lvpack >> (4 * j)) & 15u);
-                const LevLds lv = s_lv[lu];
-                int i0[3];
-                float fr[3];
+                if (ok[jj] && lu != lprev) {
+                    const LevLds lv = s_lv[lu];
+                    uint32_t i0[3];
+                    float fr[3];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const int s = (int)field(lv.raw, a);
-                    const double ul = ldexp(u[a], -s);
-                    const int b = (iu[a] >> field(lv.sh, a)) << A.Blog;
-                    const double q = ul + 0.5 - (double)b;
-                    i0[a] = (int)q;
-                    fr[a] = (float)(q - (double)i0[a]);
+                    for (int a = 0; a < 3; ++a) {
+                        const int sft = (int)field(lv.raw, a);
+                        const double ul = ldexp(u[a], -sft);
+                        const int bo = (iu[a] >> field(lv.sh, a)) << A.Blog;
+                        const double q = ul + 0.5 - (double)bo;
+                        const int qi = (int)q;
+                        i0[a] = (uint32_t)qi;
+                        fr[a] = (float)(q - (double)qi);
+                    }
+                    idx = (i0[2] * E + i0[1]) * E + i0[0];
+                    fr0 = fr[0];
+                    fr1 = fr[1];
+                    fr2 = fr[2];
+                    lprev = lu;
                 }
-                const uint8_t *base = A.slots + (size_t)slot[j] * A.slot_stride;
-                const uint32_t E = (uint32_t)A.E;
-                const uint32_t idx = ((uint32_t)i0[2] * E + (uint32_t)i0[1]) * E + (uint32_t)i0[0];
-                const float v000 = voxel<BPV>(base, idx), v100 = voxel<BPV>(base, idx + 1);
-                const float v010 = voxel<BPV>(base, idx + E), v110 = voxel<BPV>(base, idx + E + 1);
-                const float v001 = voxel<BPV>(base, idx + E * E), v101 = voxel<BPV>(base, idx + E * E + 1);
-                const float v011 = voxel<BPV>(base, idx + E * E + E), v111 = voxel<BPV>(base, idx + E * E + E + 1);
-                const float c00 = v000 + (v100 - v000) * fr[0];
-                const float c10 = v010 + (v110 - v010) * fr[0];
-                const float c01 = v001 + (v101 - v001) * fr[0];
-                const float c11 = v011 + (v111 - v011) * fr[0];
-                const float e0 = c00 + (c10 - c00) * fr[1];
-                const float e1 = c01 + (c11 - c01) * fr[1];
-                const float v = e0 + (e1 - e0) * fr[2];
+                fq[jj][0] = fr0;
+                fq[jj][1] = fr1;
+                fq[jj][2] = fr2;
+                // a channel without a slot reads offset 0 of slot 0 (always
+                // inside the pool) and its result is discarded
+                const uint8_t *base = A.slots + (ok[jj] ? (size_t)slot[j] * A.slot_stride + (size_t)idx * BPV : 0);
+                w[jj][0] = vpair<BPV>(base);
+                w[jj][1] = vpair<BPV>(base + (size_t)E * BPV);
+                w[jj][2] = vpair<BPV>(base + (size_t)E * E * BPV);
+                w[jj][3] = vpair<BPV>(base + (size_t)(E * E + E) * BPV);
+            }
+#pragma unroll
+            for (int jj = 0; jj < kGroup; ++jj) {
+                const int j = g + jj;
+                if (!ok[jj]) continue;
+                const float f0 = fq[jj][0], f1 = fq[jj][1], f2 = fq[jj][2];
+                float v00[2], v10[2], v01[2], v11[2];
+                unpack<BPV>(w[jj][0], v00);
+                unpack<BPV>(w[jj][1], v10);
+                unpack<BPV>(w[jj][2], v01);
+                unpack<BPV>(w[jj][3], v11);
+                const float c00 = v00[0] + (v00[1] - v00[0]) * f0;
+                const float c10 = v10[0] + (v10[1] - v10[0]) * f0;
+                const float c01 = v01[0] + (v01[1] - v01[0]) * f0;
+                const float c11 = v11[0] + (v11[1] - v11[0]) * f0;
+                const float e0 = c00 + (c10 - c00) * f1;
+                const float e1 = c01 + (c11 - c01) * f1;
+                const float v = e0 + (e1 - e0) * f2;
                 const ChanLds ch = s_ch[j];
                 float x = (v - ch.w0) * ch.iw;
                 x = fminf(fmaxf(x, 0.0f), 1.0f);
@@ -377,10 +496,10 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
                 sr += al * r;
                 sg += al * gg;
                 sbl += al * bb;
-                if (AOV) A.aov[((size_t)py * A.W + px) * L + lu] += 1;
+                if (AOV) A.aov[((size_t)py * A.W + px) * L + (int)((lvpack >> (4 * j)) & 15u)] += 1;
             }
-            // keep one channel's gathers in flight at a time: bounds register
-            // pressure (occupancy) instead of interleaving all channels
+            // the next group's loads are issued after this group is used:
+            // bounds the registers held by loads in flight
             asm volatile("" ::: "memory");
         }
         if (sa > 0.0f) {

@@ -1,7 +1,7 @@
 // Multi-request rendering for the serving loop (an addition to the paper's
 // method): one persistent kernel renders a batch of frame requests of
 // different viewports, channel subsets and transfer functions over the
-// shared cache and octree.  Workgroups pop 32 x 16-pixel tiles from a device
+// shared cache and octree.  Workgroups pop 32 x 32-pixel tiles from a device
 // queue; when a tile belongs to another request than the previous one, the
 // workgroup stages that request's descriptor and tables in LDS.  Every pixel
 // runs the same per-ray code as the frame kernel, so a request's image does
@@ -32,10 +32,10 @@ struct ServeHeader {
 
 
 template <int NV, int BPV>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(4)))
     k_serve(const ServeHeader *__restrict__ hdr, const RenderArgs *__restrict__ descs,
             const uint32_t *__restrict__ tiles, uint32_t *__restrict__ queue) {
-    extern __shared__ float4 s_tf[];  // [NV][256]
+    extern __shared__ float4 s_tf[];  // [NV][256] tables, then [NV][kRenderLanes] slot words
     __shared__ RenderArgs sA;
     __shared__ ChanLds s_ch[NV];
     __shared__ uint32_t s_runs[NV * kMaxRuns];
@@ -62,9 +62,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
         }
         const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
         const int px = tx * 32 + (wv & 3) * 8 + (ln & 7);
-        const int py = ty * 16 + (wv >> 2) * 8 + (ln >> 3);
+        const int py = ty * 32 + (wv >> 2) * 8 + (ln >> 3);
         uint32_t st[5] = {0, 0, 0, 0, 0};
-        render_pixel<NV, BPV, false>(sA, px, py, px < sA.W && py < sA.H, s_tf, s_ch, s_runs, s_lv, s_nd, st);
+        const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
+        render_pixel<NV, BPV, false>(sA, px, py, px < sA.W && py < sA.H, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
         if (sA.stats) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
@@ -118,7 +119,7 @@ static inline uint32_t *serve_queue(const ro_server *s, int h) {
 template <int NV, int BPV>
 static hipError_t serve_attr() {
     return hipFuncSetAttribute((const void *)k_serve<NV, BPV>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(sizeof(float4) * 256 * NV));
+                               (int)render_lds_bytes(NV));
 }
 
 template <int NV, int BPV>
@@ -129,8 +130,7 @@ static void serve_launch_t(const ro_server *s, int h, hipStream_t st) {
     const uint32_t *dt = (const uint32_t *)(d + sizeof(ServeHeader) + (size_t)s->max_req * sizeof(RenderArgs));
     uint32_t *q = serve_queue(s, h);
     hipLaunchKernelGGL(k_serve_reset, dim3(1), dim3(64), 0, st, q);
-    hipLaunchKernelGGL((k_serve<NV, BPV>), dim3(2 * s->ncu), dim3(512), sizeof(float4) * 256 * NV, st, dh, dd, dt,
-                       q);
+    hipLaunchKernelGGL((k_serve<NV, BPV>), dim3(s->ncu), dim3(kRenderLanes), render_lds_bytes(NV), st, dh, dd, dt, q);
 }
 
 // Device work of one submission from half h: copy, queue reset, kernel.
@@ -226,8 +226,8 @@ extern "C" ro_status ro_serve_prepare(ro_server *s, uint32_t n, const ro_frame_d
         ro_status vs = validate_frame(s->tree, &fds[r], rgba[r]);
         if (vs) return vs;
         RO_CHECK(!(fds[r].flags & RO_RENDER_AOV), RO_E_ARG, "AOV output is not served");
-        RO_CHECK(fds[r].width <= 8192 * 32 && fds[r].height <= 8192 * 16, RO_E_ARG, "viewport too large");
-        const uint32_t tw = (uint32_t)(fds[r].width + 31) / 32, th = (uint32_t)(fds[r].height + 15) / 16;
+        RO_CHECK(fds[r].width <= 8192 * 32 && fds[r].height <= 8192 * 32, RO_E_ARG, "viewport too large");
+        const uint32_t tw = (uint32_t)(fds[r].width + 31) / 32, th = (uint32_t)(fds[r].height + 31) / 32;
         RO_CHECK(tw * th <= s->max_tiles - nt, RO_E_CAPACITY, "batch exceeds %u tiles", s->max_tiles);
         nt += tw * th;
         maxvis = fds[r].n_vis > maxvis ? fds[r].n_vis : maxvis;
@@ -250,7 +250,7 @@ extern "C" ro_status ro_serve_prepare(ro_server *s, uint32_t n, const ro_frame_d
         memcpy(&hd[r], &A, sizeof(A));
         // a request's tiles are consecutive: a workgroup re-stages its LDS
         // tables only when it crosses into the next request
-        const uint32_t tw = (uint32_t)(fds[r].width + 31) / 32, th = (uint32_t)(fds[r].height + 15) / 16;
+        const uint32_t tw = (uint32_t)(fds[r].width + 31) / 32, th = (uint32_t)(fds[r].height + 31) / 32;
         for (uint32_t y = 0; y < th; ++y)
             for (uint32_t x = 0; x < tw; ++x) ht[nt++] = (r << 26) | (y << 13) | x;
     }

@@ -89,7 +89,8 @@ class Request:
 
     @property
     def tiles(self):
-        return ((self.W + 31) // 32) * ((self.H + 15) // 16)
+        tw, th = resoct.SERVE_TILE
+        return ((self.W + tw - 1) // tw) * ((self.H + th - 1) // th)
 
     @property
     def image_bytes(self):
