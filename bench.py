@@ -529,6 +529,7 @@ def main():
         "channel_samples_per_s": ch_samples / (t1 - t0),
         "render_samples_per_s": samples / (np.sum(render_ms) / 1000.0),
         "uploads_per_frame": float(np.mean([len(p) for p in plans])),
+        "lane_busy": float(st[0]) / max(float(st[5]), 1.0),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_render", "alg_bytes_per_launch": float(np.mean(alg_bytes))},

@@ -290,7 +290,9 @@ typedef struct {
                                       samples evaluated, [1] channel samples read from bricks,
                                       [2] channel samples whose desired brick was missing,
                                       [3] (leaf, level) visits, [4] channel samples in leaves
-                                      that are not empty for the channel; [5..7] zero */
+                                      that are not empty for the channel, [5] lane slots of
+                                      the wave stepping iterations ([0] / [5] = share of
+                                      lanes busy); [6..7] zero */
 } ro_frame_desc;
 
 /* Renders into rgba_dev[H][W][4] (float, premultiplied) and updates the

@@ -29,7 +29,7 @@ constexpr int kWavesX = 4, kWavesY = kRenderLanes / 256;
 constexpr int kTileW = kWavesX * kWaveW, kTileH = kWavesY * kWaveH;
 
 template <int NV, int BPV, bool AOV>
-__global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(4))) k_render(const RenderArgs A) {
+__global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(kRenderLanes / 256))) k_render(const RenderArgs A) {
     extern __shared__ float4 s_tf[];  // [NV][256] tables, then [NV][kRenderLanes] slot words
     __shared__ ChanLds s_ch[NV];
     __shared__ uint32_t s_runs[NV * kMaxRuns];
@@ -42,13 +42,13 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
     const int px = tx * kTileW + (wv % kWavesX) * kWaveW + (ln % kWaveW);
     const int py = ty * kTileH + (wv / kWavesX) * kWaveH + (ln / kWaveW);
-    uint32_t st[5] = {0, 0, 0, 0, 0};
+    uint32_t st[6] = {0, 0, 0, 0, 0, 0};
     const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
     render_pixel<NV, BPV, AOV>(A, px, py, px < A.W && py < A.H, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
     if (A.stats) {
         // every lane of the workgroup is here: reduce over the wave, one atomic per wave
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
+        for (int q = 0; q < 6; ++q) {
             uint32_t v = st[q];
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -131,7 +131,13 @@ __device__ __forceinline__ uint32_t node_at(const NodeLds &nd, int x, int y, int
 }
 
 // Lanes per workgroup of the render and serve kernels.
-constexpr int kRenderLanes = 1024;
+#ifndef RO_LANES
+#define RO_LANES 1024
+#endif
+#ifndef RO_GROUP
+#define RO_GROUP 4
+#endif
+constexpr int kRenderLanes = RO_LANES;
 
 // Dynamic LDS of a workgroup: NV transfer-function tables, then one slot
 // word per lane and visible channel.
@@ -152,12 +158,12 @@ template <int NV, int BPV, bool AOV>
 __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, const int py, const bool valid,
                                              const float4 *s_tf,
                                              const ChanLds *s_ch, const uint32_t *s_runs, const LevLds *s_lv,
-                                             const NodeLds *s_nd, uint32_t stats[5], LdsSlots slot) {
+                                             const NodeLds *s_nd, uint32_t stats[6], LdsSlots slot) {
     const int nvis = A.nvis;
     const int D = A.depth;
     const int L = A.L;
     const int m = A.m;
-    constexpr int kGroup = NV < 4 ? NV : 4;  // channels whose gathers are in flight together
+    constexpr int kGroup = NV < RO_GROUP ? NV : RO_GROUP;  // channels whose loads are in flight together
 
     // ---- ray in L0 voxel units
     double o[3], d[3];
@@ -227,7 +233,7 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
     uint32_t emask = 0, missmask = 0;
     uint64_t lvpack = 0;
     uint32_t nvisit = 0;
-    uint32_t st_samples = 0, st_reads = 0, st_miss = 0, st_visits = 0, st_nonempty = 0;
+    uint32_t st_samples = 0, st_reads = 0, st_miss = 0, st_visits = 0, st_nonempty = 0, st_iters = 0;
     const uint32_t vismask = (nvis >= 32) ? 0xFFFFFFFFu : ((1u << nvis) - 1u);
     int lc[3] = {-1, -1, -1};  // L0 origin of the last visited leaf (none yet)
 #pragma unroll
@@ -270,6 +276,7 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
             k += need;
             continue;
         }
+        ++st_iters;  // a stepping iteration of the wave (lane busy or idle)
         if (!active) continue;
         if (k < skip_to) {
             ++k;
@@ -525,6 +532,7 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
     stats[2] = st_miss;
     stats[3] = st_visits;
     stats[4] = st_nonempty;
+    stats[5] = st_iters;
 }
 
 // Workgroup set-up: stage the frame's transfer functions, zero-alpha runs,

@@ -32,7 +32,7 @@ struct ServeHeader {
 
 
 template <int NV, int BPV>
-__global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(kRenderLanes / 256)))
     k_serve(const ServeHeader *__restrict__ hdr, const RenderArgs *__restrict__ descs,
             const uint32_t *__restrict__ tiles, uint32_t *__restrict__ queue) {
     extern __shared__ float4 s_tf[];  // [NV][256] tables, then [NV][kRenderLanes] slot words
@@ -63,12 +63,12 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
         const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
         const int px = tx * 32 + (wv & 3) * 8 + (ln & 7);
         const int py = ty * 32 + (wv >> 2) * 8 + (ln >> 3);
-        uint32_t st[5] = {0, 0, 0, 0, 0};
+        uint32_t st[6] = {0, 0, 0, 0, 0, 0};
         const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
         render_pixel<NV, BPV, false>(sA, px, py, px < sA.W && py < sA.H, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
         if (sA.stats) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
+            for (int q = 0; q < 6; ++q) {
                 uint32_t v = st[q];
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
