@@ -338,7 +338,7 @@ def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True):
 
 
 def prefetch_bench(train_seeds=tuple(range(1000, 1010)), eval_seeds=tuple(range(1010, 1015)), n_frames=120,
-                   U=512, lr=1e-3):
+                   U=512, lr=1e-3, train_steps=1, threshold=0.5, gate=0.5):
     """Learned prefetcher against plain request-driven streaming on the
     4-channel 2048 x 2048 x 64 cell volume (2 GiB cache, 1024 x 1024
     perspective views, upload budget U bricks per frame): the network trains
@@ -371,7 +371,9 @@ def prefetch_bench(train_seeds=tuple(range(1000, 1010)), eval_seeds=tuple(range(
     t = time.perf_counter()
     train = []
     for s in train_seeds:
-        _, sm = run_path(scene, store, path(s), chans, W, H, U, step, "learned", net, empty, lr=lr)
+        _, sm = run_path(scene, store, path(s), chans, W, H, U, step, "learned", net, empty, lr=lr,
+                         train_steps=train_steps, threshold=threshold, gate=gate)
+        sm.pop("missing_curve")
         train.append(sm)
         log(f"train path {s}: {sm}")
     t_train = time.perf_counter() - t
@@ -379,10 +381,12 @@ def prefetch_bench(train_seeds=tuple(range(1000, 1010)), eval_seeds=tuple(range(
     for s in eval_seeds:
         cams = path(s)
         _, sp = run_path(scene, store, cams, chans, W, H, U, step, "plain", None, empty)
-        _, sl = run_path(scene, store, cams, chans, W, H, U, step, "learned", net, empty, lr=lr)
+        _, sl = run_path(scene, store, cams, chans, W, H, U, step, "learned", net, empty, lr=lr,
+                         train_steps=train_steps, threshold=threshold, gate=gate)
         ev.append({"seed": s, "plain": sp, "learned": sl})
-        log(f"eval path {s}: plain {sp}")
-        log(f"eval path {s}: learned {sl}")
+        brief = lambda d: {k: v for k, v in d.items() if k != "missing_curve"}
+        log(f"eval path {s}: plain {brief(sp)}")
+        log(f"eval path {s}: learned {brief(sl)}")
 
     def agg(key, pol):
         v = [e[pol][key] for e in ev]
@@ -390,6 +394,7 @@ def prefetch_bench(train_seeds=tuple(range(1000, 1010)), eval_seeds=tuple(range(
 
     out = {"workload": "4ch-2048x2048x64-u16 cells, 2 GiB cache, 1024x1024 perspective, random paths",
            "frames_per_path": n_frames, "upload_budget": U, "train_paths": list(train_seeds),
+           "policy": {"lr": lr, "train_steps": train_steps, "threshold": threshold, "precision_gate": gate},
            "eval_paths": list(eval_seeds), "train_s": t_train,
            "summary": {pol: {k: agg(k, pol) for k in ("first_below_1pct", "stays_below_1pct", "mean_missing",
                                                        "bytes_streamed")} for pol in ("plain", "learned")},
@@ -413,6 +418,10 @@ def main():
     ap.add_argument("--rate", type=float, default=400.0, help="serving arrival rate, requests/s")
     ap.add_argument("--prefetch-only", action="store_true",
                     help="only the learned-prefetcher evaluation (10 training, 5 held-out paths)")
+    ap.add_argument("--pf-lr", type=float, default=1e-3)
+    ap.add_argument("--pf-steps", type=int, default=1, help="Adam steps per frame")
+    ap.add_argument("--pf-threshold", type=float, default=0.5, help="candidate probability threshold")
+    ap.add_argument("--pf-gate", type=float, default=0.5, help="precision below which the plain policy is used")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the measurement, copy a 1 GiB buffer three times (a plain copy kernel of "
                          "known size, to scale hardware byte counters)")
@@ -427,7 +436,8 @@ def main():
     from paper_2309_04393_amd.pipeline import GpuScene
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.prefetch_only:
-        print(json.dumps({"prefetch": prefetch_bench()}), flush=True)
+        print(json.dumps({"prefetch": prefetch_bench(lr=args.pf_lr, train_steps=args.pf_steps,
+                                                     threshold=args.pf_threshold, gate=args.pf_gate)}), flush=True)
         return
     if args.serve_only:
         print(json.dumps({"serving": serve_bench(args.rate, args.serve)}), flush=True)

@@ -41,10 +41,11 @@ class BrickStore:
 
 class StreamingLoop:
     def __init__(self, scene, store: BrickStore, chans, W, H, U, step, policy="plain", net=None, lr=1e-3,
-                 threshold=0.5, lod_bias=1.0, train=True):
+                 threshold=0.5, lod_bias=1.0, train=True, train_steps=1, gate=0.5):
         self.s, self.store = scene, store
         self.chans, self.W, self.H, self.U, self.step = chans, W, H, U, step
         self.policy, self.net, self.lr, self.thr, self.lod_bias, self.train = policy, net, lr, threshold, lod_bias, train
+        self.train_steps, self.gate = train_steps, gate
         self.tf = scene.tf_tensor(chans)
         self.out = torch.empty(W * H * 4, dtype=torch.float32, device="cuda")
         self.stats = torch.zeros(8, dtype=torch.int64, device="cuda")
@@ -78,7 +79,8 @@ class StreamingLoop:
             self.pf.features(fd, x)
             if f >= 4 and self.train:
                 self.pf.labels(self.y, self.m)
-                self.net.train_step(self.ring[(f - 4) % 5], self.y, self.m, self.lr)
+                for _ in range(self.train_steps):
+                    self.net.train_step(self.ring[(f - 4) % 5], self.y, self.m, self.lr)
             # precision of the extra bricks streamed four frames ago
             if (f - 4) in self.extra:
                 old = self.extra.pop(f - 4)
@@ -88,7 +90,7 @@ class StreamingLoop:
                     self.hits.append(int((h[dense] != 0).sum()))
                     self.tries.append(len(old))
             room = self.U - len(plain)
-            if room > 0 and self.precision() >= 0.5:
+            if room > 0 and self.precision() >= self.gate:
                 self.net.forward(x, self.z)
                 cid, cpr = self.pf.candidates(self.z, self.thr)
                 if len(cid):
@@ -139,18 +141,18 @@ def first_below(log, thr=0.01, hold=1):
 
 
 def run_path(scene, store, cams, chans, W, H, U, step, policy, net=None, empty_state=None, lr=1e-3,
-             train=True, lod_bias=1.0, threshold=0.5):
+             train=True, lod_bias=1.0, threshold=0.5, train_steps=1, gate=0.5):
     """One camera path from an empty cache; returns the loop's per-frame
     log and a summary."""
     if empty_state is not None:
         restore_state(scene, empty_state)
     loop = StreamingLoop(scene, store, chans, W, H, U, step, policy=policy, net=net, lr=lr,
-                         threshold=threshold, lod_bias=lod_bias, train=train)
+                         threshold=threshold, lod_bias=lod_bias, train=train, train_steps=train_steps, gate=gate)
     for f, cam in enumerate(cams, start=1):
         loop.frame(f, cam)
     log = loop.log
     miss = np.array([r["missing"] for r in log])
-    return log, dict(frames=len(log), first_below_1pct=first_below(log, 0.01),
+    return log, dict(missing_curve=[round(float(x), 5) for x in miss],frames=len(log), first_below_1pct=first_below(log, 0.01),
                      stays_below_1pct=first_below(log, 0.01, hold=5),
                      mean_missing=float(miss.mean()), bytes_streamed=int(sum(r["bytes"] for r in log)),
                      uploads=int(sum(r["uploads"] for r in log)), extra=int(sum(r["extra"] for r in log)),
