@@ -42,6 +42,28 @@ METRIC = "samples/s & ms/frame @1080p 16ch; HBM GB/s; frames-to-converge; p99 la
 HBM_PEAK_GBS = 8000.0
 
 
+def profiled_traffic(workload):
+    """HBM bytes per k_render launch from the committed rocprofv3 summary of
+    this workload (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known
+    size), or None when the summary is missing or the kernel's sources have
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_render-{workload}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    if "<!-- roofline" not in txt:
+        return None
+    block = txt.split("<!-- roofline", 1)[1].split("-->", 1)[0]
+    kv = dict(line.split(": ", 1) for line in block.strip().splitlines() if ": " in line)
+    h = hashlib.sha256()
+    for f in ("render_core.h", "render.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2309_04393_amd", "csrc", f), "rb").read())
+    if kv.get("kernel_sources_sha256") != h.hexdigest() or kv.get("workload") != workload:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -541,7 +563,7 @@ def main():
         "uploads_per_frame": float(np.mean([len(p) for p in plans])),
         "lane_busy": float(st[0]) / max(float(st[5]), 1.0),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(cfg["name"]),
                      "kernel": "k_render", "alg_bytes_per_launch": float(np.mean(alg_bytes))},
     }
     if args.copy_calibration:
