@@ -296,7 +296,10 @@ typedef struct {
 } ro_frame_desc;
 
 /* Renders into rgba_dev[H][W][4] (float, premultiplied) and updates the
- * miss counters and slot stamps.  Asynchronous. */
+ * miss counters and slot stamps.  Asynchronous.  The kernel's work queue
+ * counter lives in the octree's scratch buffer, so frames of one octree are
+ * rendered one at a time (in stream order); use the server below for
+ * concurrent requests. */
 ro_status ro_render(ro_octree *t, const ro_frame_desc *fd, float *rgba_dev, void *stream);
 
 /* ------------------------------------------------------------- predictor */

@@ -1,7 +1,8 @@
 // Ray-guided mixed-resolution multi-channel ray casting over the residency
 // octree (Sec. 6.1, Alg. 1; Sec. 6.2; Sec. 6 implementation notes).
 //
-// One lane per pixel; a 1024-lane workgroup covers a 32 x 32 pixel tile.
+// One lane per ray; persistent 1024-lane workgroups whose waves take
+// 8 x 8-pixel blocks from a queue.
 // Sample positions and every integer decision derived from them (box, leaf,
 // brick, level) are computed in FP64; interpolation, transfer functions and
 // the channel mix in FP32; the compositing state in FP64.  Per lane, the
@@ -21,15 +22,25 @@
 
 namespace ro {
 
-// 1024-lane workgroups (16 waves of 8 x 8 pixels, a 32 x 32 pixel tile):
-// one workgroup per CU holds one copy of the frame's LDS tables plus the
-// per-lane slot words, at 4 waves per SIMD.
-constexpr int kWaveW = 8, kWaveH = 8;
-constexpr int kWavesX = 4, kWavesY = kRenderLanes / 256;
-constexpr int kTileW = kWavesX * kWaveW, kTileH = kWavesY * kWaveH;
+// 1024-lane workgroups, one per CU: one copy of the frame's LDS tables plus
+// the per-lane slot words, at 4 waves per SIMD.
 
+// Lanes refill only when the whole wave is idle: a wave then takes a whole
+// new 8 x 8 block and its rays start together.  Refilling single lanes as
+// their rays end keeps more lanes busy (91 % against 70 %) but spreads a
+// wave's samples over different depths and cache lines, and measured 3.4x
+// slower on the 16-channel 1080p frame; refilling from 16 idle lanes 1.5x
+// slower.
+#ifndef RO_MIN_IDLE
+#define RO_MIN_IDLE 64
+#endif
+
+// Persistent grid (one workgroup per CU) whose waves take 8 x 8-pixel blocks
+// from a device counter independently of each other, so a CU never waits
+// for the slowest wave of a workgroup before taking new work.
 template <int NV, int BPV, bool AOV>
-__global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(kRenderLanes / 256))) k_render(const RenderArgs A) {
+__global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(kRenderLanes / 256)))
+    k_render(const RenderArgs A, uint32_t *counter, uint32_t n_blocks, uint32_t tiles_x) {
     extern __shared__ float4 s_tf[];  // [NV][256] tables, then [NV][kRenderLanes] slot words
     __shared__ ChanLds s_ch[NV];
     __shared__ uint32_t s_runs[NV * kMaxRuns];
@@ -38,47 +49,57 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
 
     stage_frame<NV>(A, s_tf, s_ch, s_runs, s_lv, s_nd);
 
-    const int tx = blockIdx.x, ty = blockIdx.y;
-    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    const int px = tx * kTileW + (wv % kWavesX) * kWaveW + (ln % kWaveW);
-    const int py = ty * kTileH + (wv / kWavesX) * kWaveH + (ln / kWaveW);
+    BlockQueue q;
+    q.counter = counter;
+    q.n_blocks = n_blocks;
+    q.tiles_x = tiles_x;
+    q.W = A.W;
+    q.H = A.H;
+    q.min_idle = RO_MIN_IDLE;
     uint32_t st[6] = {0, 0, 0, 0, 0, 0};
     const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
-    render_pixel<NV, BPV, AOV>(A, px, py, px < A.W && py < A.H, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
+    render_rays<NV, BPV, AOV>(A, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
     if (A.stats) {
         // every lane of the workgroup is here: reduce over the wave, one atomic per wave
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            uint32_t v = st[q];
+        for (int j = 0; j < 6; ++j) {
+            uint32_t v = st[j];
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            if ((threadIdx.x & 63) == 0 && v) atomicAdd(&A.stats[q], (unsigned long long)v);
+            if ((threadIdx.x & 63) == 0 && v) atomicAdd(&A.stats[j], (unsigned long long)v);
         }
     }
 }
 
+struct QueueLaunch {
+    dim3 grid;
+    uint32_t *counter;
+    uint32_t n_blocks, tiles_x;
+};
+
 template <int NV, int BPV, bool AOV>
-static hipError_t launch_one(const RenderArgs &A, dim3 grid, hipStream_t s) {
+static hipError_t launch_one(const RenderArgs &A, const QueueLaunch &Q, hipStream_t s) {
     const size_t lds = render_lds_bytes(NV);
     hipError_t e = hipFuncSetAttribute((const void *)k_render<NV, BPV, AOV>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_render<NV, BPV, AOV>), grid, dim3(kRenderLanes), lds, s, A);
+    hipLaunchKernelGGL((k_render<NV, BPV, AOV>), Q.grid, dim3(kRenderLanes), lds, s, A, Q.counter, Q.n_blocks,
+                       Q.tiles_x);
     return hipGetLastError();
 }
 
 template <int NV, int BPV>
-static hipError_t launch_nv(const RenderArgs &A, bool aov, dim3 grid, hipStream_t s) {
-    return aov ? launch_one<NV, BPV, true>(A, grid, s) : launch_one<NV, BPV, false>(A, grid, s);
+static hipError_t launch_nv(const RenderArgs &A, bool aov, const QueueLaunch &Q, hipStream_t s) {
+    return aov ? launch_one<NV, BPV, true>(A, Q, s) : launch_one<NV, BPV, false>(A, Q, s);
 }
 
 template <int BPV>
-static hipError_t launch_bpv(const RenderArgs &A, bool aov, dim3 grid, hipStream_t s) {
-    if (A.nvis <= 1) return launch_nv<1, BPV>(A, aov, grid, s);
-    if (A.nvis <= 2) return launch_nv<2, BPV>(A, aov, grid, s);
-    if (A.nvis <= 4) return launch_nv<4, BPV>(A, aov, grid, s);
-    if (A.nvis <= 8) return launch_nv<8, BPV>(A, aov, grid, s);
-    return launch_nv<16, BPV>(A, aov, grid, s);
+static hipError_t launch_bpv(const RenderArgs &A, bool aov, const QueueLaunch &Q, hipStream_t s) {
+    if (A.nvis <= 1) return launch_nv<1, BPV>(A, aov, Q, s);
+    if (A.nvis <= 2) return launch_nv<2, BPV>(A, aov, Q, s);
+    if (A.nvis <= 4) return launch_nv<4, BPV>(A, aov, Q, s);
+    if (A.nvis <= 8) return launch_nv<8, BPV>(A, aov, Q, s);
+    return launch_nv<16, BPV>(A, aov, Q, s);
 }
 
 // Kernel arguments of one frame (validated by the caller).
@@ -173,9 +194,21 @@ ro_status render_device(ro_octree *tr, const ro_frame_desc *fd, float *rgba, hip
     RenderArgs A;
     ro_status st = build_render_args(tr, fd, rgba, A);
     if (st) return st;
-    dim3 grid((fd->width + kTileW - 1) / kTileW, (fd->height + kTileH - 1) / kTileH);
+    int dev = 0, ncu = 0;
+    RO_HIP(hipGetDevice(&dev));
+    RO_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    QueueLaunch Q;
+    const uint32_t tiles_x = (uint32_t)(fd->width + 31) / 32, tiles_y = (uint32_t)(fd->height + 31) / 32;
+    Q.tiles_x = tiles_x;
+    Q.n_blocks = tiles_x * tiles_y * 16;
+    // the block counter is the last word block of the octree's scratch buffer
+    // (residency work items use the rest); cleared by a kernel, not a memset
+    Q.counter = (uint32_t *)((uint8_t *)tr->b.scratch + tr->scratch_bytes - 256);
+    Q.grid = dim3((unsigned)(ncu > 0 ? ncu : 256));
+    st = launch_fill_u32(Q.counter, 1, 0u, s);
+    if (st) return st;
     const bool aov = (fd->flags & RO_RENDER_AOV) != 0;
-    RO_HIP(g.bpv == 1 ? launch_bpv<1>(A, aov, grid, s) : launch_bpv<2>(A, aov, grid, s));
+    RO_HIP(g.bpv == 1 ? launch_bpv<1>(A, aov, Q, s) : launch_bpv<2>(A, aov, Q, s));
     return RO_OK;
 }
 

@@ -154,93 +154,191 @@ struct LdsSlots {
     __device__ __forceinline__ uint32_t &operator[](int j) { return p[(uint32_t)j * stride]; }
 };
 
-template <int NV, int BPV, bool AOV>
-__device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, const int py, const bool valid,
-                                             const float4 *s_tf,
-                                             const ChanLds *s_ch, const uint32_t *s_runs, const LevLds *s_lv,
-                                             const NodeLds *s_nd, uint32_t stats[6], LdsSlots slot) {
+// Pixel sources of the stepping loop.  A source hands a lane its first
+// pixel and, if it refills, further pixels when lanes of the wave are idle.
+//
+// OnePixel: the lane's one pixel (the serving kernel's tile lanes).
+struct OnePixel {
+    static constexpr bool kRefill = false;
+    int px, py;
+    bool valid;
+    __device__ __forceinline__ bool first(int &x, int &y, bool &v) {
+        x = px;
+        y = py;
+        v = valid;
+        return true;
+    }
+    __device__ __forceinline__ bool refill(uint64_t, int &, int &, bool &) { return false; }
+    __device__ __forceinline__ bool more() const { return false; }
+};
+
+// BlockQueue: waves take 8 x 8-pixel blocks from a device counter (blocks of
+// a 32 x 32 tile are consecutive, tiles in raster order).  Lanes whose ray
+// ended take the next pixels of the wave's current block, in lane order of
+// a ballot of the idle lanes (prefix ranks), and the wave takes a new block
+// when the current one is used up.  Counter reads and block state are
+// wave-uniform.
+struct BlockQueue {
+    static constexpr bool kRefill = true;
+    uint32_t *counter;
+    uint32_t n_blocks, tiles_x;
+    int W, H;
+    int min_idle;     // refill when at least this many lanes are idle
+    uint32_t block;   // current block (wave-uniform)
+    uint32_t used;    // its pixels handed out
+    bool exhausted;
+
+    __device__ __forceinline__ uint32_t pop() {
+        uint32_t b = 0;
+        if ((threadIdx.x & 63) == 0) b = atomicAdd(counter, 1u);
+        return (uint32_t)__shfl((int)b, 0, 64);
+    }
+    __device__ __forceinline__ void pixel(uint32_t b, uint32_t i, int &x, int &y, bool &v) const {
+        const uint32_t t = b >> 4;
+        x = (int)((t % tiles_x) * 32 + (b & 3u) * 8 + (i & 7u));
+        y = (int)((t / tiles_x) * 32 + ((b >> 2) & 3u) * 8 + (i >> 3));
+        v = x < W && y < H;
+    }
+    __device__ __forceinline__ bool more() const { return !exhausted; }
+    __device__ __forceinline__ bool first(int &x, int &y, bool &v) {
+        block = pop();
+        used = 64;
+        exhausted = block >= n_blocks;
+        if (exhausted) return false;
+        pixel(block, threadIdx.x & 63, x, y, v);
+        return true;
+    }
+    // want: ballot of the idle lanes; returns whether this lane got a pixel
+    __device__ __forceinline__ bool refill(uint64_t want, int &x, int &y, bool &v) {
+        if (exhausted || __popcll(want) < (unsigned)min_idle) return false;
+        const uint32_t ln = threadIdx.x & 63;
+        const bool me = (want >> ln) & 1ull;
+        const uint32_t r = (uint32_t)__popcll(want & ((1ull << ln) - 1ull));
+        const uint32_t n = (uint32_t)__popcll(want);
+        const uint32_t left = 64 - used;
+        bool got = false;
+        if (me && r < left) {
+            pixel(block, used + r, x, y, v);
+            got = true;
+        }
+        if (n > left) {
+            const uint32_t nb = pop();
+            if (nb >= n_blocks) {
+                exhausted = true;
+                used = 64;
+            } else {
+                if (me && r >= left) {
+                    pixel(nb, r - left, x, y, v);
+                    got = true;
+                }
+                block = nb;
+                used = n - left;
+            }
+        } else {
+            used += n;
+        }
+        return got;
+    }
+};
+
+template <int NV, int BPV, bool AOV, class Source>
+__device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, const float4 *s_tf,
+                                            const ChanLds *s_ch, const uint32_t *s_runs, const LevLds *s_lv,
+                                            const NodeLds *s_nd, uint32_t stats[6], LdsSlots slot) {
     const int nvis = A.nvis;
     const int D = A.depth;
     const int L = A.L;
     const int m = A.m;
     constexpr int kGroup = NV < RO_GROUP ? NV : RO_GROUP;  // channels whose loads are in flight together
+    const double one_minus_term = 1.0 - (double)A.term;
+    const uint32_t vismask = (nvis >= 32) ? 0xFFFFFFFFu : ((1u << nvis) - 1u);
+    const int s0 = A.start_level;
+    const bool noskip = (A.flags & RO_RENDER_NO_SKIP) != 0;
+    const NodeLds leafl = s_nd[D];
+    uint32_t st_samples = 0, st_reads = 0, st_miss = 0, st_visits = 0, st_nonempty = 0, st_iters = 0;
 
-    // ---- ray in L0 voxel units
-    double o[3], d[3];
-    {
+    // ---- per-ray state
+    int px = 0, py = 0;
+    bool has = false;  // the lane holds a ray (finished or not)
+    double o[3] = {0, 0, 0}, d[3] = {0, 0, 0};
+    double Cr = 0, Cg = 0, Cb = 0, Tr = 1.0;
+    float *out = nullptr;
+    bool done = true;
+    long long k = 0, kend = -1, skip_to = 0;  // the lane is inside an empty node while k < skip_to
+    uint32_t cur_leaf = kInvalid;
+    int cur_lod = -1, lod = 0;
+    uint32_t emask = 0, missmask = 0;
+    uint64_t lvpack = 0;
+    uint32_t nvisit = 0;
+    int lc[3] = {-1, -1, -1};  // L0 origin of the last visited leaf (none yet)
+
+    // ray set-up in L0 voxel units, box interval, first sample index
+    auto start = [&](int x, int y, bool valid) {
+        px = x;
+        py = y;
+        has = true;
         const double a = (double)(2 * px + 1 - A.W) / (double)A.W;
         const double b = (double)(A.H - 2 * py - 1) / (double)A.H;
         double ow[3], dw[3];
         if (A.proj == RO_PROJ_ORTHO) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                ow[k] = A.eye[k] + a * A.tx * A.R[k] + b * A.ty * A.U[k];
-                dw[k] = A.F[k];
+            for (int q = 0; q < 3; ++q) {
+                ow[q] = A.eye[q] + a * A.tx * A.R[q] + b * A.ty * A.U[q];
+                dw[q] = A.F[q];
             }
         } else {
             double n = 0;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                ow[k] = A.eye[k];
-                dw[k] = A.F[k] + a * A.tx * A.R[k] + b * A.ty * A.U[k];
-                n += dw[k] * dw[k];
+            for (int q = 0; q < 3; ++q) {
+                ow[q] = A.eye[q];
+                dw[q] = A.F[q] + a * A.tx * A.R[q] + b * A.ty * A.U[q];
+                n += dw[q] * dw[q];
             }
             n = sqrt(n);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) dw[k] = dw[k] / n;
+            for (int q = 0; q < 3; ++q) dw[q] = dw[q] / n;
         }
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            o[k] = ow[k] / A.sp[k];
-            d[k] = dw[k] / A.sp[k];
+        for (int q = 0; q < 3; ++q) {
+            o[q] = ow[q] / A.sp[q];
+            d[q] = dw[q] / A.sp[q];
         }
-    }
-    double Cr = 0, Cg = 0, Cb = 0, Tr = 1.0;
-    const double one_minus_term = 1.0 - (double)A.term;
-    float *out = valid ? A.rgba + ((size_t)py * A.W + px) * 4 : nullptr;
-
-    // ---- box interval
-    double t0 = -INFINITY, t1 = INFINITY;
-    bool hit = true;
+        Cr = Cg = Cb = 0.0;
+        Tr = 1.0;
+        out = valid ? A.rgba + ((size_t)py * A.W + px) * 4 : nullptr;
+        double t0 = -INFINITY, t1 = INFINITY;
+        bool hit = true;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        if (d[k] == 0.0) {
-            if (o[k] < 0.0 || o[k] >= (double)A.dims[k]) hit = false;
-            continue;
+        for (int q = 0; q < 3; ++q) {
+            if (d[q] == 0.0) {
+                if (o[q] < 0.0 || o[q] >= (double)A.dims[q]) hit = false;
+                continue;
+            }
+            double u = (0.0 - o[q]) / d[q], v = ((double)A.dims[q] - o[q]) / d[q];
+            if (u > v) {
+                const double sw = u;
+                u = v;
+                v = sw;
+            }
+            t0 = fmax(t0, u);
+            t1 = fmin(t1, v);
         }
-        double u = (0.0 - o[k]) / d[k], v = ((double)A.dims[k] - o[k]) / d[k];
-        if (u > v) {
-            const double s = u;
-            u = v;
-            v = s;
-        }
-        t0 = fmax(t0, u);
-        t1 = fmin(t1, v);
-    }
-    // lanes whose ray misses the volume (or lie outside the image) stay in
-    // the loop below as inactive lanes: every lane of the wave takes part in
-    // the wave-level decisions
-    bool done = !valid || !hit || t0 > t1;
-    long long k = done ? 0 : (long long)floor(t0 / A.step) - 1;
-    if (k < 0) k = 0;
-    const long long kend = done ? -1 : (long long)ceil(t1 / A.step) + 1;
-    long long skip_to = 0;  // the lane is inside an empty node while k < skip_to
-
-    // ---- visit state
-    uint32_t cur_leaf = kInvalid;
-    int cur_lod = -1, lod = 0;
-    while (lod + 1 < L && (unsigned long long)k >= s_lv[lod + 1].K) ++lod;
-    uint32_t emask = 0, missmask = 0;
-    uint64_t lvpack = 0;
-    uint32_t nvisit = 0;
-    uint32_t st_samples = 0, st_reads = 0, st_miss = 0, st_visits = 0, st_nonempty = 0, st_iters = 0;
-    const uint32_t vismask = (nvis >= 32) ? 0xFFFFFFFFu : ((1u << nvis) - 1u);
-    int lc[3] = {-1, -1, -1};  // L0 origin of the last visited leaf (none yet)
+        done = !valid || !hit || t0 > t1;
+        k = done ? 0 : (long long)floor(t0 / A.step) - 1;
+        if (k < 0) k = 0;
+        kend = done ? -1 : (long long)ceil(t1 / A.step) + 1;
+        skip_to = 0;
+        cur_leaf = kInvalid;
+        cur_lod = -1;
+        lod = 0;
+        while (lod + 1 < L && (unsigned long long)k >= s_lv[lod + 1].K) ++lod;
+        emask = missmask = 0;
+        lvpack = 0;
+        nvisit = 0;
+        lc[0] = lc[1] = lc[2] = -1;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) slot[j] = kInvalid;
-    const int s0 = A.start_level;
-    const bool noskip = (A.flags & RO_RENDER_NO_SKIP) != 0;
-    const NodeLds leafl = s_nd[D];
+        for (int j = 0; j < NV; ++j) slot[j] = kInvalid;
+    };
 
     auto flush = [&]() {
         if (missmask && nvisit) {
@@ -260,18 +358,51 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
         nvisit = 0;
     };
 
+    auto finish = [&]() {
+        flush();
+        if (out) {
+            out[0] = (float)Cr;
+            out[1] = (float)Cg;
+            out[2] = (float)Cb;
+            out[3] = (float)(1.0 - Tr);
+        }
+        has = false;
+    };
+
+    {
+        int x = 0, y = 0;
+        bool v = false;
+        if (src.first(x, y, v)) start(x, y, v);
+    }
+
     // Wave-coherent stepping: lanes advance one sample per iteration, so the
     // lanes of a wave (neighbouring pixels) sample at the same t and share
     // cache lines; a lane inside an empty node idles, and the wave jumps
     // ahead only by the smallest skip over its active lanes.  The samples a
-    // lane evaluates are exactly those it would evaluate on its own.
+    // lane evaluates are exactly those it would evaluate on its own.  A lane
+    // whose ray ended writes its pixel and, with a refilling source, starts
+    // the next pixel of the wave's block.
     while (true) {
-        const bool active = !done && k <= kend;
+        if (has && (done || k > kend)) finish();
+        if (Source::kRefill) {
+            const uint64_t want = __ballot(!has);
+            if (want) {
+                int x = 0, y = 0;
+                bool v = false;
+                if (src.refill(want, x, y, v)) start(x, y, v);
+            }
+        }
+        const bool active = has && !done && k <= kend;
         const long long gap = skip_to - k;
         uint32_t need = !active ? 0xFFFFFFFFu : (gap > 0 ? (gap < 0x7FFFFFFFll ? (uint32_t)gap : 0x7FFFFFFFu) : 0u);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) need = min(need, (uint32_t)__shfl_xor((int)need, o, 64));
-        if (need == 0xFFFFFFFFu) break;  // no active lane left in the wave
+        if (need == 0xFFFFFFFFu) {
+            // no lane is stepping: the wave ends once no lane holds a ray and
+            // the source has nothing more (rays that just ended retire above)
+            if (!__any(has) && !src.more()) break;
+            continue;
+        }
         if (need > 0) {
             k += need;
             continue;
@@ -519,13 +650,6 @@ __device__ __forceinline__ void render_pixel(const RenderArgs &A, const int px, 
             if (Tr <= one_minus_term) done = true;
         }
         ++k;
-    }
-    flush();
-    if (out) {
-        out[0] = (float)Cr;
-        out[1] = (float)Cg;
-        out[2] = (float)Cb;
-        out[3] = (float)(1.0 - Tr);
     }
     stats[0] = st_samples;
     stats[1] = st_reads;

@@ -65,7 +65,8 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
         const int py = ty * 32 + (wv >> 2) * 8 + (ln >> 3);
         uint32_t st[6] = {0, 0, 0, 0, 0, 0};
         const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
-        render_pixel<NV, BPV, false>(sA, px, py, px < sA.W && py < sA.H, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
+        OnePixel one{px, py, px < sA.W && py < sA.H};
+        render_rays<NV, BPV, false>(sA, one, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
         if (sA.stats) {
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
