@@ -360,7 +360,7 @@ def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True):
 
 
 def prefetch_bench(train_seeds=tuple(range(1000, 1010)), eval_seeds=tuple(range(1010, 1015)), n_frames=120,
-                   U=512, lr=1e-3, train_steps=1, threshold=0.5, gate=0.5):
+                   U=512, lr=3e-3, train_steps=4, threshold=0.5, gate=0.5):
     """Learned prefetcher against plain request-driven streaming on the
     4-channel 2048 x 2048 x 64 cell volume (2 GiB cache, 1024 x 1024
     perspective views, upload budget U bricks per frame): the network trains
@@ -418,7 +418,7 @@ def prefetch_bench(train_seeds=tuple(range(1000, 1010)), eval_seeds=tuple(range(
            "frames_per_path": n_frames, "upload_budget": U, "train_paths": list(train_seeds),
            "policy": {"lr": lr, "train_steps": train_steps, "threshold": threshold, "precision_gate": gate},
            "eval_paths": list(eval_seeds), "train_s": t_train,
-           "summary": {pol: {k: agg(k, pol) for k in ("first_below_1pct", "stays_below_1pct", "mean_missing",
+           "summary": {pol: {k: agg(k, pol) for k in ("frames_to_converge", "first_below_1pct", "mean_missing",
                                                        "bytes_streamed")} for pol in ("plain", "learned")},
            "paths": ev}
     del store, scene
@@ -440,8 +440,8 @@ def main():
     ap.add_argument("--rate", type=float, default=400.0, help="serving arrival rate, requests/s")
     ap.add_argument("--prefetch-only", action="store_true",
                     help="only the learned-prefetcher evaluation (10 training, 5 held-out paths)")
-    ap.add_argument("--pf-lr", type=float, default=1e-3)
-    ap.add_argument("--pf-steps", type=int, default=1, help="Adam steps per frame")
+    ap.add_argument("--pf-lr", type=float, default=3e-3)
+    ap.add_argument("--pf-steps", type=int, default=4, help="Adam steps per frame")
     ap.add_argument("--pf-threshold", type=float, default=0.5, help="candidate probability threshold")
     ap.add_argument("--pf-gate", type=float, default=0.5, help="precision below which the plain policy is used")
     ap.add_argument("--copy-calibration", action="store_true",
