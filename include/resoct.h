@@ -297,7 +297,7 @@ typedef struct {
 
 /* Renders into rgba_dev[H][W][4] (float, premultiplied) and updates the
  * miss counters and slot stamps.  Asynchronous.  The kernel's work queue
- * counter lives in the octree's scratch buffer, so frames of one octree are
+ * counters live in the octree's scratch buffer, so frames of one octree are
  * rendered one at a time (in stream order); use the server below for
  * concurrent requests. */
 ro_status ro_render(ro_octree *t, const ro_frame_desc *fd, float *rgba_dev, void *stream);
@@ -369,7 +369,7 @@ ro_status ro_pf_candidates(ro_prefetch *p, const float *z_dev, float threshold, 
 /* Batched rendering for a serving loop (an addition to the paper's method):
  * one persistent kernel renders up to 64 frame requests of different
  * viewports, channel subsets, transfer functions and cameras over the shared
- * cache and octree; its workgroups pop 32 x 32-pixel tiles from a device
+ * cache and octree; its workgroups pop 32 x 24-pixel tiles from a device
  * queue.  Each pixel runs the same code as ro_render, so a request's image is
  * the same alone and in any batch.
  *

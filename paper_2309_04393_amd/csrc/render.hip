@@ -22,8 +22,10 @@
 
 namespace ro {
 
-// 1024-lane workgroups, one per CU: one copy of the frame's LDS tables plus
-// the per-lane slot words, at 4 waves per SIMD.
+// Workgroups of kRenderLanes lanes (768: 3 waves per SIMD, up to 168 VGPRs,
+// no spills), one per CU: one copy of the frame's LDS tables plus the
+// per-lane slot words.  1024 lanes (4 waves per SIMD, 128 VGPRs) spill and
+// measured 1-10 % slower, 512 lanes 35 % slower.
 
 // Lanes refill only when the whole wave is idle: a wave then takes a whole
 // new 8 x 8 block and its rays start together.  Refilling single lanes as
@@ -164,6 +166,8 @@ ro_status build_render_args(ro_octree *tr, const ro_frame_desc *fd, float *rgba,
         }
     }
     A.nvis = fd->n_vis;
+    A.ident = fd->n_vis == g.m && g.m % 4 == 0;
+    for (int j = 0; j < fd->n_vis; ++j) A.ident = A.ident && fd->vis[j] == j;
     for (int j = 0; j < fd->n_vis; ++j) {
         A.vis[j] = fd->vis[j];
         A.lo[j] = fd->lod_lo[j];
@@ -201,8 +205,9 @@ ro_status render_device(ro_octree *tr, const ro_frame_desc *fd, float *rgba, hip
     const uint32_t tiles_x = (uint32_t)(fd->width + 31) / 32, tiles_y = (uint32_t)(fd->height + 31) / 32;
     Q.tiles_x = tiles_x;
     Q.n_blocks = tiles_x * tiles_y * 16;
-    // the block counter is the last word block of the octree's scratch buffer
-    // (residency work items use the rest); cleared by a kernel, not a memset
+    // the block counter is in the last 256 bytes of the octree's scratch
+    // buffer (residency work items use the rest); cleared by a kernel, not a
+    // memset
     Q.counter = (uint32_t *)((uint8_t *)tr->b.scratch + tr->scratch_bytes - 256);
     Q.grid = dim3((unsigned)(ncu > 0 ? ncu : 256));
     st = launch_fill_u32(Q.counter, 1, 0u, s);

@@ -20,6 +20,7 @@ struct RenderArgs {
     int32_t nvis;
     float term;
     uint32_t frame, flags;
+    int32_t ident;  // visible slot j shows channel j for every channel, and m % 4 == 0
     // uniform tables copied to LDS by the workgroup
     int32_t vis[kMaxC], lo[kMaxC], hi[kMaxC];
     uint32_t W0[kMaxC], W1[kMaxC];
@@ -132,12 +133,14 @@ __device__ __forceinline__ uint32_t node_at(const NodeLds &nd, int x, int y, int
 
 // Lanes per workgroup of the render and serve kernels.
 #ifndef RO_LANES
-#define RO_LANES 1024
+#define RO_LANES 768
 #endif
 #ifndef RO_GROUP
 #define RO_GROUP 4
 #endif
 constexpr int kRenderLanes = RO_LANES;
+// Serving tiles: 4 x (lanes / 256) waves of 8 x 8 pixels.
+constexpr int kServeTileW = 32, kServeTileH = kRenderLanes / 32;
 
 // Dynamic LDS of a workgroup: NV transfer-function tables, then one slot
 // word per lane and visible channel.
@@ -173,14 +176,15 @@ struct OnePixel {
 };
 
 // BlockQueue: waves take 8 x 8-pixel blocks from a device counter (blocks of
-// a 32 x 32 tile are consecutive, tiles in raster order).  Lanes whose ray
-// ended take the next pixels of the wave's current block, in lane order of
-// a ballot of the idle lanes (prefix ranks), and the wave takes a new block
-// when the current one is used up.  Counter reads and block state are
-// wave-uniform.
+// a 32 x 32 tile are consecutive, tiles in raster order), so the waves of
+// all CUs sweep the image together and share the Infinity Cache; splitting
+// the blocks into one range per XCD measured 4 % slower.  Lanes whose ray
+// ended take the next pixels of the wave's block, in lane order of a ballot
+// of the idle lanes (prefix ranks), once at least min_idle lanes are idle.
+// Counter reads and block state are wave-uniform.
 struct BlockQueue {
     static constexpr bool kRefill = true;
-    uint32_t *counter;
+    uint32_t *counter;  // zero at launch
     uint32_t n_blocks, tiles_x;
     int W, H;
     int min_idle;     // refill when at least this many lanes are idle
@@ -271,6 +275,8 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     uint64_t lvpack = 0;
     uint32_t nvisit = 0;
     int lc[3] = {-1, -1, -1};  // L0 origin of the last visited leaf (none yet)
+    uint32_t last_key = kInvalid;  // (level, cell) of the last visit when uniform
+    uint32_t have = 0;             // channels with a slot from the last visit
 
     // ray set-up in L0 voxel units, box interval, first sample index
     auto start = [&](int x, int y, bool valid) {
@@ -336,6 +342,8 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         lvpack = 0;
         nvisit = 0;
         lc[0] = lc[1] = lc[2] = -1;
+        last_key = kInvalid;
+        have = 0;
 #pragma unroll
         for (int j = 0; j < NV; ++j) slot[j] = kInvalid;
     };
@@ -460,8 +468,17 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     for (int g = 0; g < NV; g += kGroup) {
                         if (g >= nvis) break;
                         uint32_t mm[kGroup];
+                        if (kGroup == 4 && A.ident) {
+                            // channels g..g+3 are one aligned 16-byte load
+                            const uint4 v = *(const uint4 *)(nm + g);
+                            mm[0] = v.x;
+                            mm[kGroup > 1 ? 1 : 0] = v.y;
+                            mm[kGroup > 2 ? 2 : 0] = v.z;
+                            mm[kGroup > 3 ? 3 : 0] = v.w;
+                        } else {
 #pragma unroll
-                        for (int jj = 0; jj < kGroup; ++jj) mm[jj] = g + jj < nvis ? nm[s_ch[g + jj].c] : 0u;
+                            for (int jj = 0; jj < kGroup; ++jj) mm[jj] = g + jj < nvis ? nm[s_ch[g + jj].c] : 0u;
+                        }
 #pragma unroll
                         for (int jj = 0; jj < kGroup; ++jj) {
                             const int j = g + jj;
@@ -499,48 +516,94 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
             ++st_visits;
             missmask = 0;
             lvpack = 0;
-            // residency masks of the leaf, then the page-table entries of the
-            // chosen bricks, kGroup channels per batch of loads
+            // Residency masks of the leaf give each channel the level it
+            // samples (finest resident at or above the desired one).
             const uint16_t *lm = A.mask + (size_t)leaf * m;
+            uint32_t look = 0;  // channels with a resident brick to look up
 #pragma unroll
             for (int g = 0; g < NV; g += kGroup) {
                 if (g >= nvis) break;
                 uint32_t mk[kGroup];
+                if (kGroup == 4 && A.ident) {
+                    const uint2 v = *(const uint2 *)(lm + g);
+                    mk[0] = v.x & 0xFFFFu;
+                    mk[kGroup > 1 ? 1 : 0] = v.x >> 16;
+                    mk[kGroup > 2 ? 2 : 0] = v.y & 0xFFFFu;
+                    mk[kGroup > 3 ? 3 : 0] = v.y >> 16;
+                } else {
 #pragma unroll
-                for (int jj = 0; jj < kGroup; ++jj) {
-                    const int j = g + jj;
-                    mk[jj] = (j < nvis && !((emask >> j) & 1u)) ? (uint32_t)lm[s_ch[j].c] : 0u;
+                    for (int jj = 0; jj < kGroup; ++jj) mk[jj] = g + jj < nvis ? (uint32_t)lm[s_ch[g + jj].c] : 0u;
                 }
 #pragma unroll
                 for (int jj = 0; jj < kGroup; ++jj) {
                     const int j = g + jj;
-                    uint32_t ns = kInvalid;
                     if (j < nvis && !((emask >> j) & 1u)) {
                         const ChanLds ch = s_ch[j];
                         const int ls = min(max(lod, ch.lo), ch.hi);
                         const uint32_t mj = mk[jj] >> ls;
                         if (!(mj & 1u)) missmask |= 1u << j;
                         if (mj) {
-                            const int lu = ls + __builtin_ctz(mj);
-                            const LevLds lv = s_lv[lu];
-                            ns = A.pt[brick_dense(lv, (uint32_t)ch.c, A.per_channel, iu[0] >> field(lv.sh, 0),
-                                                  iu[1] >> field(lv.sh, 1), iu[2] >> field(lv.sh, 2))];
-                            lvpack |= (uint64_t)lu << (4 * j);
+                            lvpack |= (uint64_t)(ls + __builtin_ctz(mj)) << (4 * j);
+                            look |= 1u << j;
                         }
                     }
-                    mk[jj] = ns;
+                }
+            }
+            // When every looked-up channel samples one level, its bricks are
+            // the same grid cell in each channel: if that cell and level are
+            // those of the previous visit, the slots found then still hold
+            // (the page table does not change during a frame).
+            uint32_t key = kInvalid;
+            if (look) {
+                const int lu0 = (int)((lvpack >> (4 * __builtin_ctz(look))) & 15u);
+                bool uniform = true;
+#pragma unroll
+                for (int j = 0; j < NV; ++j)
+                    if (((look >> j) & 1u) && (int)((lvpack >> (4 * j)) & 15u) != lu0) uniform = false;
+                if (uniform) {
+                    const LevLds lv = s_lv[lu0];
+                    key = brick_dense(lv, 0u, 0u, iu[0] >> field(lv.sh, 0), iu[1] >> field(lv.sh, 1),
+                                      iu[2] >> field(lv.sh, 2)) |
+                          ((uint32_t)lu0 << 28);
+                }
+            }
+            const uint32_t reuse = (key != kInvalid && key == last_key) ? have : 0u;
+            uint32_t nhave = 0;
+#pragma unroll
+            for (int g = 0; g < NV; g += kGroup) {
+                if (g >= nvis) break;
+                uint32_t ns[kGroup];
+#pragma unroll
+                for (int jj = 0; jj < kGroup; ++jj) {
+                    const int j = g + jj;
+                    ns[jj] = kInvalid;
+                    if ((look >> j) & 1u) {
+                        if ((reuse >> j) & 1u) {
+                            ns[jj] = slot[j];
+                        } else {
+                            const int lu = (int)((lvpack >> (4 * j)) & 15u);
+                            const LevLds lv = s_lv[lu];
+                            ns[jj] = A.pt[brick_dense(lv, (uint32_t)s_ch[j].c, A.per_channel, iu[0] >> field(lv.sh, 0),
+                                                      iu[1] >> field(lv.sh, 1), iu[2] >> field(lv.sh, 2))];
+                        }
+                    }
                 }
 #pragma unroll
                 for (int jj = 0; jj < kGroup; ++jj) {
                     const int j = g + jj;
                     if (j >= nvis) break;
-                    const uint32_t ns = mk[jj];
-                    if (ns == kInvalid) lvpack &= ~((uint64_t)15u << (4 * j));
-                    else if (ns != slot[j]) A.stamp[ns] = A.frame;
-                    slot[j] = ns;
+                    if (ns[jj] == kInvalid) {
+                        lvpack &= ~((uint64_t)15u << (4 * j));
+                    } else {
+                        nhave |= 1u << j;
+                        if (ns[jj] != slot[j]) A.stamp[ns[jj]] = A.frame;
+                    }
+                    slot[j] = ns[jj];
                 }
                 asm volatile("" ::: "memory");
             }
+            have = nhave;
+            last_key = key;
         }
         ++nvisit;
         ++st_samples;

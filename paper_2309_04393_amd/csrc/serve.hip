@@ -1,7 +1,7 @@
 // Multi-request rendering for the serving loop (an addition to the paper's
 // method): one persistent kernel renders a batch of frame requests of
 // different viewports, channel subsets and transfer functions over the
-// shared cache and octree.  Workgroups pop 32 x 32-pixel tiles from a device
+// shared cache and octree.  Workgroups pop 32 x 24-pixel tiles from a device
 // queue; when a tile belongs to another request than the previous one, the
 // workgroup stages that request's descriptor and tables in LDS.  Every pixel
 // runs the same per-ray code as the frame kernel, so a request's image does
@@ -61,8 +61,8 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
             cur = req;
         }
         const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-        const int px = tx * 32 + (wv & 3) * 8 + (ln & 7);
-        const int py = ty * 32 + (wv >> 2) * 8 + (ln >> 3);
+        const int px = tx * kServeTileW + (wv & 3) * 8 + (ln & 7);
+        const int py = ty * kServeTileH + (wv >> 2) * 8 + (ln >> 3);
         uint32_t st[6] = {0, 0, 0, 0, 0, 0};
         const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
         OnePixel one{px, py, px < sA.W && py < sA.H};
@@ -227,8 +227,10 @@ extern "C" ro_status ro_serve_prepare(ro_server *s, uint32_t n, const ro_frame_d
         ro_status vs = validate_frame(s->tree, &fds[r], rgba[r]);
         if (vs) return vs;
         RO_CHECK(!(fds[r].flags & RO_RENDER_AOV), RO_E_ARG, "AOV output is not served");
-        RO_CHECK(fds[r].width <= 8192 * 32 && fds[r].height <= 8192 * 32, RO_E_ARG, "viewport too large");
-        const uint32_t tw = (uint32_t)(fds[r].width + 31) / 32, th = (uint32_t)(fds[r].height + 31) / 32;
+        RO_CHECK(fds[r].width <= 8192 * kServeTileW && fds[r].height <= 8192 * kServeTileH, RO_E_ARG,
+                 "viewport too large");
+        const uint32_t tw = (uint32_t)(fds[r].width + kServeTileW - 1) / kServeTileW,
+                       th = (uint32_t)(fds[r].height + kServeTileH - 1) / kServeTileH;
         RO_CHECK(tw * th <= s->max_tiles - nt, RO_E_CAPACITY, "batch exceeds %u tiles", s->max_tiles);
         nt += tw * th;
         maxvis = fds[r].n_vis > maxvis ? fds[r].n_vis : maxvis;
@@ -251,7 +253,8 @@ extern "C" ro_status ro_serve_prepare(ro_server *s, uint32_t n, const ro_frame_d
         memcpy(&hd[r], &A, sizeof(A));
         // a request's tiles are consecutive: a workgroup re-stages its LDS
         // tables only when it crosses into the next request
-        const uint32_t tw = (uint32_t)(fds[r].width + 31) / 32, th = (uint32_t)(fds[r].height + 31) / 32;
+        const uint32_t tw = (uint32_t)(fds[r].width + kServeTileW - 1) / kServeTileW,
+                       th = (uint32_t)(fds[r].height + kServeTileH - 1) / kServeTileH;
         for (uint32_t y = 0; y < th; ++y)
             for (uint32_t x = 0; x < tw; ++x) ht[nt++] = (r << 26) | (y << 13) | x;
     }

@@ -474,7 +474,7 @@ class PrefetchRows:
 
 
 SERVE_GRAPH = 1
-SERVE_TILE = (32, 32)  # pixels per tile of the serving queue (width, height)
+SERVE_TILE = (32, 24)  # pixels per tile of the serving queue (width, height)
 _sig("ro_serve_query", c_i32, [c_u32, c_u32, _P(c_sz)])
 _sig("ro_serve_create", c_i32, [c_vp, c_u32, c_u32, c_vp, _P(c_vp)])
 _sig("ro_serve_destroy", None, [c_vp])
