@@ -369,7 +369,8 @@ ro_status ro_pf_candidates(ro_prefetch *p, const float *z_dev, float threshold, 
 /* Batched rendering for a serving loop (an addition to the paper's method):
  * one persistent kernel renders up to 64 frame requests of different
  * viewports, channel subsets, transfer functions and cameras over the shared
- * cache and octree; its workgroups pop 32 x 24-pixel tiles from a device
+ * cache and octree; its workgroups pop work items (up to 96 blocks of 8 x 8
+ * pixels of one request; ro_serve_work_items counts them) from a device
  * queue.  Each pixel runs the same code as ro_render, so a request's image is
  * the same alone and in any batch.
  *
@@ -385,7 +386,10 @@ ro_status ro_pf_candidates(ro_prefetch *p, const float *z_dev, float threshold, 
 #define RO_SERVE_GRAPH 1u
 typedef struct ro_server ro_server;
 ro_status ro_serve_query(uint32_t max_requests, uint32_t max_tiles, size_t *device_bytes);
-/* max_requests in 1..64 per batch; max_tiles in 1..2^24 per batch. */
+/* Work items of a width x height request. */
+ro_status ro_serve_work_items(int32_t width, int32_t height, uint32_t *items);
+/* max_requests in 1..64 per batch; max_tiles (work items) in 1..2^24 per
+ * batch. */
 ro_status ro_serve_create(ro_octree *t, uint32_t max_requests, uint32_t max_tiles, void *device_buf,
                           ro_server **out);
 /* Waits for outstanding batches, then frees the server's resources. */

@@ -54,6 +54,7 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
     BlockQueue q;
     q.counter = counter;
     q.n_blocks = n_blocks;
+    q.offset = 0;
     q.tiles_x = tiles_x;
     q.W = A.W;
     q.H = A.H;

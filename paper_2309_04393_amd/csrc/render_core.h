@@ -139,8 +139,8 @@ __device__ __forceinline__ uint32_t node_at(const NodeLds &nd, int x, int y, int
 #define RO_GROUP 4
 #endif
 constexpr int kRenderLanes = RO_LANES;
-// Serving tiles: 4 x (lanes / 256) waves of 8 x 8 pixels.
-constexpr int kServeTileW = 32, kServeTileH = kRenderLanes / 32;
+// Serving work items: up to kSegBlocks 8 x 8-pixel blocks of one request.
+constexpr uint32_t kSegBlocks = 96;
 
 // Dynamic LDS of a workgroup: NV transfer-function tables, then one slot
 // word per lane and visible channel.
@@ -184,8 +184,9 @@ struct OnePixel {
 // Counter reads and block state are wave-uniform.
 struct BlockQueue {
     static constexpr bool kRefill = true;
-    uint32_t *counter;  // zero at launch
-    uint32_t n_blocks, tiles_x;
+    uint32_t *counter;  // zero at launch (device or LDS word)
+    uint32_t n_blocks;  // blocks this queue hands out: offset .. offset + n_blocks - 1
+    uint32_t offset, tiles_x;
     int W, H;
     int min_idle;     // refill when at least this many lanes are idle
     uint32_t block;   // current block (wave-uniform)
@@ -198,6 +199,7 @@ struct BlockQueue {
         return (uint32_t)__shfl((int)b, 0, 64);
     }
     __device__ __forceinline__ void pixel(uint32_t b, uint32_t i, int &x, int &y, bool &v) const {
+        b += offset;
         const uint32_t t = b >> 4;
         x = (int)((t % tiles_x) * 32 + (b & 3u) * 8 + (i & 7u));
         y = (int)((t / tiles_x) * 32 + ((b >> 2) & 3u) * 8 + (i >> 3));

@@ -1,13 +1,14 @@
 // Multi-request rendering for the serving loop (an addition to the paper's
 // method): one persistent kernel renders a batch of frame requests of
 // different viewports, channel subsets and transfer functions over the
-// shared cache and octree.  Workgroups pop 32 x 24-pixel tiles from a device
-// queue; when a tile belongs to another request than the previous one, the
-// workgroup stages that request's descriptor and tables in LDS.  Every pixel
-// runs the same per-ray code as the frame kernel, so a request's image does
-// not depend on what else is in the batch.
+// shared cache and octree.  Workgroups pop work items (up to 96 blocks of
+// 8 x 8 pixels of one request) from a device queue; when an item belongs to
+// another request than the previous one, the workgroup stages that
+// request's descriptor and tables in LDS.  Every pixel runs the same per-ray
+// code as the frame kernel, so a request's image does not depend on what
+// else is in the batch.
 //
-// The host prepares descriptors and the tile list in pinned host memory owned
+// The host prepares descriptors and the work list in pinned host memory owned
 // by the server.  There are two halves used alternately, each with its own
 // device copy, queue counter and stream, so a batch can be prepared while the
 // previous one renders and the tail of one batch overlaps the head of the
@@ -31,27 +32,35 @@ struct ServeHeader {
 };
 
 
+// Work items ("segments") are up to kSegBlocks consecutive 8 x 8-pixel
+// blocks of one request (blocks of a 32 x 32 tile consecutive, tiles in
+// raster order).  A workgroup takes a segment, stages the request's tables
+// if it changed, and its waves take the segment's blocks from an LDS counter
+// one at a time, so waves that finish early take more blocks; the workgroup
+// waits for its slowest wave only once per segment.
 template <int NV, int BPV>
 __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(kRenderLanes / 256)))
     k_serve(const ServeHeader *__restrict__ hdr, const RenderArgs *__restrict__ descs,
-            const uint32_t *__restrict__ tiles, uint32_t *__restrict__ queue) {
+            const uint32_t *__restrict__ segs, uint32_t *__restrict__ queue) {
     extern __shared__ float4 s_tf[];  // [NV][256] tables, then [NV][kRenderLanes] slot words
     __shared__ RenderArgs sA;
     __shared__ ChanLds s_ch[NV];
     __shared__ uint32_t s_runs[NV * kMaxRuns];
     __shared__ LevLds s_lv[kMaxL];
     __shared__ NodeLds s_nd[kMaxD + 1];
-    __shared__ uint32_t s_tile;
-    const uint32_t n_tiles = hdr->n_tiles;
+    __shared__ uint32_t s_seg, s_next;
+    const uint32_t n_segs = hdr->n_tiles;
     int cur = -1;
     for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1u);
+        if (threadIdx.x == 0) {
+            s_seg = atomicAdd(queue, 1u);
+            s_next = 0;
+        }
         __syncthreads();
-        const uint32_t tile = s_tile;
-        if (tile >= n_tiles) break;
-        const uint32_t tw = tiles[tile];
-        const int req = (int)(tw >> 26);
-        const int tx = (int)(tw & 0x1FFFu), ty = (int)((tw >> 13) & 0x1FFFu);
+        const uint32_t seg = s_seg;
+        if (seg >= n_segs) break;
+        const uint32_t sw = segs[seg];
+        const int req = (int)(sw >> 26);
         if (req != cur) {
             const uint32_t *src = (const uint32_t *)(descs + req);
             uint32_t *dst = (uint32_t *)&sA;
@@ -60,23 +69,29 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
             stage_frame<NV>(sA, s_tf, s_ch, s_runs, s_lv, s_nd);
             cur = req;
         }
-        const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-        const int px = tx * kServeTileW + (wv & 3) * 8 + (ln & 7);
-        const int py = ty * kServeTileH + (wv >> 2) * 8 + (ln >> 3);
+        const uint32_t tiles_x = ((uint32_t)sA.W + 31) / 32, tiles_y = ((uint32_t)sA.H + 31) / 32;
+        const uint32_t first = (sw & 0x3FFFFFFu) * kSegBlocks, n_blk = tiles_x * tiles_y * 16;
+        BlockQueue q;
+        q.counter = &s_next;
+        q.n_blocks = min(kSegBlocks, n_blk - first);
+        q.offset = first;
+        q.tiles_x = tiles_x;
+        q.W = sA.W;
+        q.H = sA.H;
+        q.min_idle = 64;
         uint32_t st[6] = {0, 0, 0, 0, 0, 0};
         const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
-        OnePixel one{px, py, px < sA.W && py < sA.H};
-        render_rays<NV, BPV, false>(sA, one, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
+        render_rays<NV, BPV, false>(sA, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
         if (sA.stats) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                uint32_t v = st[q];
+            for (int j = 0; j < 6; ++j) {
+                uint32_t v = st[j];
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-                if ((threadIdx.x & 63) == 0 && v) atomicAdd(&sA.stats[q], (unsigned long long)v);
+                if ((threadIdx.x & 63) == 0 && v) atomicAdd(&sA.stats[j], (unsigned long long)v);
             }
         }
-        __syncthreads();  // sA / LDS tables and s_tile are reused by the next tile
+        __syncthreads();  // sA, the LDS tables, s_seg and s_next are reused by the next segment
     }
 }
 
@@ -107,6 +122,19 @@ struct ro_server {
     hipGraph_t graph[2];
     hipGraphExec_t exec[2];
 };
+
+// Work items of a W x H request: its 8 x 8 blocks (16 per 32 x 32 tile) in
+// groups of kSegBlocks.
+static uint32_t serve_segments(int W, int H) {
+    const uint64_t blocks = (uint64_t)((W + 31) / 32) * (uint64_t)((H + 31) / 32) * 16u;
+    return (uint32_t)((blocks + kSegBlocks - 1) / kSegBlocks);
+}
+
+extern "C" ro_status ro_serve_work_items(int32_t width, int32_t height, uint32_t *items) {
+    RO_CHECK(items && width > 0 && height > 0, RO_E_ARG, "bad argument");
+    *items = serve_segments(width, height);
+    return RO_OK;
+}
 
 static size_t serve_half_bytes(uint32_t max_req, uint32_t max_tiles) {
     size_t b = sizeof(ServeHeader) + (size_t)max_req * sizeof(RenderArgs) + 4 * (size_t)max_tiles;
@@ -227,12 +255,10 @@ extern "C" ro_status ro_serve_prepare(ro_server *s, uint32_t n, const ro_frame_d
         ro_status vs = validate_frame(s->tree, &fds[r], rgba[r]);
         if (vs) return vs;
         RO_CHECK(!(fds[r].flags & RO_RENDER_AOV), RO_E_ARG, "AOV output is not served");
-        RO_CHECK(fds[r].width <= 8192 * kServeTileW && fds[r].height <= 8192 * kServeTileH, RO_E_ARG,
-                 "viewport too large");
-        const uint32_t tw = (uint32_t)(fds[r].width + kServeTileW - 1) / kServeTileW,
-                       th = (uint32_t)(fds[r].height + kServeTileH - 1) / kServeTileH;
-        RO_CHECK(tw * th <= s->max_tiles - nt, RO_E_CAPACITY, "batch exceeds %u tiles", s->max_tiles);
-        nt += tw * th;
+        RO_CHECK(fds[r].width <= 65536 && fds[r].height <= 65536, RO_E_ARG, "viewport too large");
+        const uint32_t ns = serve_segments(fds[r].width, fds[r].height);
+        RO_CHECK(ns <= s->max_tiles - nt, RO_E_CAPACITY, "batch exceeds %u work items", s->max_tiles);
+        nt += ns;
         maxvis = fds[r].n_vis > maxvis ? fds[r].n_vis : maxvis;
     }
     // the half being written was submitted two batches ago: wait for it
@@ -251,12 +277,10 @@ extern "C" ro_status ro_serve_prepare(ro_server *s, uint32_t n, const ro_frame_d
             return st;
         }
         memcpy(&hd[r], &A, sizeof(A));
-        // a request's tiles are consecutive: a workgroup re-stages its LDS
-        // tables only when it crosses into the next request
-        const uint32_t tw = (uint32_t)(fds[r].width + kServeTileW - 1) / kServeTileW,
-                       th = (uint32_t)(fds[r].height + kServeTileH - 1) / kServeTileH;
-        for (uint32_t y = 0; y < th; ++y)
-            for (uint32_t x = 0; x < tw; ++x) ht[nt++] = (r << 26) | (y << 13) | x;
+        // a request's segments are consecutive: a workgroup re-stages its
+        // LDS tables only when it crosses into the next request
+        const uint32_t ns = serve_segments(fds[r].width, fds[r].height);
+        for (uint32_t i = 0; i < ns; ++i) ht[nt++] = (r << 26) | i;
     }
     hh->n_tiles = nt;
     hh->n_req = n;

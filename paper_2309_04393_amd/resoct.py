@@ -474,7 +474,6 @@ class PrefetchRows:
 
 
 SERVE_GRAPH = 1
-SERVE_TILE = (32, 24)  # pixels per tile of the serving queue (width, height)
 _sig("ro_serve_query", c_i32, [c_u32, c_u32, _P(c_sz)])
 _sig("ro_serve_create", c_i32, [c_vp, c_u32, c_u32, c_vp, _P(c_vp)])
 _sig("ro_serve_destroy", None, [c_vp])
@@ -482,6 +481,14 @@ _sig("ro_serve_prepare", c_i32, [c_vp, c_u32, c_vp, c_vp, c_i32])
 _sig("ro_serve_submit", c_i32, [c_vp, c_u32, _P(c_u64)])
 _sig("ro_serve_poll", c_i32, [c_vp, c_u64, _P(c_i32)])
 _sig("ro_serve_wait", c_i32, [c_vp, c_u64])
+_sig("ro_serve_work_items", c_i32, [c_i32, c_i32, _P(c_u32)])
+
+
+def serve_work_items(W: int, H: int) -> int:
+    """Work items (queue entries) a W x H request takes in a serving batch."""
+    n = c_u32()
+    _check(_lib.ro_serve_work_items(W, H, ctypes.byref(n)), "ro_serve_work_items")
+    return int(n.value)
 
 
 class Server:

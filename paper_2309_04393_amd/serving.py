@@ -89,8 +89,7 @@ class Request:
 
     @property
     def tiles(self):
-        tw, th = resoct.SERVE_TILE
-        return ((self.W + tw - 1) // tw) * ((self.H + th - 1) // th)
+        return resoct.serve_work_items(self.W, self.H)
 
     @property
     def image_bytes(self):

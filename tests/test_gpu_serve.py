@@ -188,7 +188,7 @@ def test_server_errors(scene):
     big = dict(rig.reqs[0], W=400, H=300)
     rig2 = Rig(scene, [big])
     with pytest.raises(resoct.ResoctError) as e:
-        srv.prepare([rig2.fd(0)], [rig2.out(0)])  # 130 tiles > 8
+        srv.prepare([rig2.fd(0)], [rig2.out(0)])  # 22 work items > 8
     assert e.value.code == -2
     with pytest.raises(resoct.ResoctError):
         srv.poll(12345)
