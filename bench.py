@@ -277,7 +277,7 @@ def leaf_mm_all(cfg):
     return _LM[key]
 
 
-def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True):
+def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True, max_batch=64):
     """Serving on the 16-channel 2048 x 2048 x 64 cell volume, every brick
     resident in a 24 GiB cache: 64 clients, Poisson arrivals at `rate`
     requests/s, viewports {256^2, 512^2, 1024^2, 1920x1080}, 3-16 channels
@@ -308,7 +308,7 @@ def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True):
     scene.tree.update_residency()
     torch.cuda.synchronize()
     log(f"serving scene: {len(ids)} bricks resident in {n_slots} slots ({time.perf_counter() - t:.1f} s)")
-    loop = ServingLoop(scene, out_budget=4 << 30, max_requests=64, max_tiles=1 << 17, graph=graph)
+    loop = ServingLoop(scene, out_budget=4 << 30, max_requests=max_batch, max_tiles=1 << 17, graph=graph)
     from paper_2309_04393_amd import resoct
     # saturated throughput: the same requests batched vs one at a time
     sub = make_trace(scene, rate, n_sat / rate, arrival_seed=3001)
@@ -331,7 +331,7 @@ def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True):
     ws = time.perf_counter() - t
     ss = float(stats.cpu().numpy()[0])
     out = {"workload": "16ch-2048x2048x64-u16 cells, all 173392 bricks resident, 24 GiB cache",
-           "clients": 64, "graph": graph,
+           "clients": 64, "graph": graph, "max_batch_requests": max_batch,
            "saturated": {"requests": len(sub), "batched_samples_per_s": sb / wb, "batched_req_per_s": len(sub) / wb,
                          "one_at_a_time_samples_per_s": ss / ws, "one_at_a_time_req_per_s": len(sub) / ws,
                          "speedup": (sb / wb) / (ss / ws), "same_samples": sb == ss}}
@@ -438,6 +438,8 @@ def main():
                     help="seconds of the serving measurement after the frame measurement (0: skip)")
     ap.add_argument("--serve-only", action="store_true", help="only the serving measurement")
     ap.add_argument("--rate", type=float, default=400.0, help="serving arrival rate, requests/s")
+    ap.add_argument("--serve-max-batch", type=int, default=64, help="requests per serving batch at most")
+    ap.add_argument("--no-prefetch", action="store_true", help="skip the learned-prefetcher evaluation")
     ap.add_argument("--prefetch-only", action="store_true",
                     help="only the learned-prefetcher evaluation (10 training, 5 held-out paths)")
     ap.add_argument("--pf-lr", type=float, default=3e-3)
@@ -462,7 +464,7 @@ def main():
                                                      threshold=args.pf_threshold, gate=args.pf_gate)}), flush=True)
         return
     if args.serve_only:
-        print(json.dumps({"serving": serve_bench(args.rate, args.serve)}), flush=True)
+        print(json.dumps({"serving": serve_bench(args.rate, args.serve, max_batch=args.serve_max_batch)}), flush=True)
         return
     cfg = config(args.config)
     vol = cfg["vol"]
@@ -590,10 +592,14 @@ def main():
                              "ambiguous_frac": float(1.0 - ok.mean())}
         except Exception as e:  # reported, not fatal
             out["cpu_baseline"] = {"error": repr(e)}
-    if args.serve > 0:
+    if args.serve > 0 or not args.no_prefetch:
         del fl, store, scene
         torch.cuda.empty_cache()
-        out["serving"] = serve_bench(args.rate, args.serve)
+    if args.serve > 0:
+        out["serving"] = serve_bench(args.rate, args.serve, max_batch=args.serve_max_batch)
+    if not args.no_prefetch:
+        pf = prefetch_bench(lr=args.pf_lr, train_steps=args.pf_steps, threshold=args.pf_threshold, gate=args.pf_gate)
+        out["prefetch"] = {k: v for k, v in pf.items() if k != "paths"}
     print(json.dumps(out), flush=True)
 
 

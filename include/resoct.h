@@ -412,6 +412,10 @@ ro_status ro_serve_submit(ro_server *s, uint32_t flags, uint64_t *ticket);
 /* *done = 1 when the batch has finished (its images and counters are
  * written), else 0. */
 ro_status ro_serve_poll(ro_server *s, uint64_t ticket, int32_t *done);
+/* *done = 1 when request r (its index in the batch) of the batch has
+ * finished: the kernel posts each request's completion to mapped host
+ * memory as soon as its last work item is written, before the batch ends. */
+ro_status ro_serve_request_done(ro_server *s, uint64_t ticket, uint32_t r, int32_t *done);
 ro_status ro_serve_wait(ro_server *s, uint64_t ticket);
 /* prepare (kernel chosen by the batch's largest channel count) + submit. */
 ro_status ro_serve_launch(ro_server *s, uint32_t n, const ro_frame_desc *fds, float *const *rgba_dev,

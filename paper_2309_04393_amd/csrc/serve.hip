@@ -24,12 +24,23 @@
 
 namespace ro {
 
-// Batch header in the mapped buffer.
+// Batch header (device copy of the prepared half).
 struct ServeHeader {
     uint32_t n_tiles;
     uint32_t n_req;
-    uint32_t pad[62];
+    uint32_t seq;              // batch ticket (low 32 bits), posted per finished request
+    uint32_t pad0;
+    uint32_t *done;            // device [max_req] finished work items per request
+    volatile uint32_t *flags;  // mapped host [max_req] completion tickets
+    uint32_t pad[56];
 };
+
+// Work items of a W x H request: its 8 x 8 blocks (16 per 32 x 32 tile) in
+// groups of kSegBlocks.
+__host__ __device__ inline uint32_t serve_segments(int W, int H) {
+    const uint64_t blocks = (uint64_t)((W + 31) / 32) * (uint64_t)((H + 31) / 32) * 16u;
+    return (uint32_t)((blocks + kSegBlocks - 1) / kSegBlocks);
+}
 
 
 // Work items ("segments") are up to kSegBlocks consecutive 8 x 8-pixel
@@ -91,12 +102,24 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
                 if ((threadIdx.x & 63) == 0 && v) atomicAdd(&sA.stats[j], (unsigned long long)v);
             }
         }
+        __threadfence();  // this item's pixels are visible device-wide before it is counted
         __syncthreads();  // sA, the LDS tables, s_seg and s_next are reused by the next segment
+        if (threadIdx.x == 0) {
+            // the request's last work item posts its completion to the host:
+            // its pixels (and those of every other item, each fenced before
+            // its count) are written before the flag
+            const uint32_t c = atomicAdd(hdr->done + req, 1u) + 1u;
+            if (c == serve_segments(sA.W, sA.H)) {
+                __threadfence_system();
+                hdr->flags[req] = hdr->seq;
+            }
+        }
     }
 }
 
-__global__ void k_serve_reset(uint32_t *queue) {
+__global__ void k_serve_reset(uint32_t *queue, uint32_t *done, uint32_t n) {
     if (threadIdx.x == 0) *queue = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) done[i] = 0;
 }
 
 ro_status build_render_args(ro_octree *tr, const ro_frame_desc *fd, float *rgba, RenderArgs &A);
@@ -110,7 +133,9 @@ struct ro_server {
     uint32_t max_req, max_tiles;
     int ncu;
     uint8_t *host;        // pinned host memory: 2 halves
-    uint8_t *dev;         // caller-owned device buffer: 2 halves + 2 queue counters
+    uint32_t *flags;      // mapped pinned host memory: [2][max_req] completion tickets
+    uint32_t *flags_dev;  // its device address
+    uint8_t *dev;         // caller-owned device buffer: 2 halves, 2 queue counters, [2][max_req] counts
     size_t half;          // bytes per half
     int cur;              // half the next prepare writes
     int ready;            // half prepared and not yet submitted (-1: none)
@@ -122,13 +147,6 @@ struct ro_server {
     hipGraph_t graph[2];
     hipGraphExec_t exec[2];
 };
-
-// Work items of a W x H request: its 8 x 8 blocks (16 per 32 x 32 tile) in
-// groups of kSegBlocks.
-static uint32_t serve_segments(int W, int H) {
-    const uint64_t blocks = (uint64_t)((W + 31) / 32) * (uint64_t)((H + 31) / 32) * 16u;
-    return (uint32_t)((blocks + kSegBlocks - 1) / kSegBlocks);
-}
 
 extern "C" ro_status ro_serve_work_items(int32_t width, int32_t height, uint32_t *items) {
     RO_CHECK(items && width > 0 && height > 0, RO_E_ARG, "bad argument");
@@ -145,6 +163,11 @@ static inline uint32_t *serve_queue(const ro_server *s, int h) {
     return (uint32_t *)(s->dev + 2 * s->half + 256 * (size_t)h);
 }
 
+// per-request finished work-item counts of half h (max_req <= 64 words)
+static inline uint32_t *serve_done(const ro_server *s, int h) {
+    return (uint32_t *)(s->dev + 2 * s->half + 512 + 256 * (size_t)h);
+}
+
 template <int NV, int BPV>
 static hipError_t serve_attr() {
     return hipFuncSetAttribute((const void *)k_serve<NV, BPV>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -158,7 +181,7 @@ static void serve_launch_t(const ro_server *s, int h, hipStream_t st) {
     const RenderArgs *dd = (const RenderArgs *)(d + sizeof(ServeHeader));
     const uint32_t *dt = (const uint32_t *)(d + sizeof(ServeHeader) + (size_t)s->max_req * sizeof(RenderArgs));
     uint32_t *q = serve_queue(s, h);
-    hipLaunchKernelGGL(k_serve_reset, dim3(1), dim3(64), 0, st, q);
+    hipLaunchKernelGGL(k_serve_reset, dim3(1), dim3(64), 0, st, q, serve_done(s, h), s->max_req);
     hipLaunchKernelGGL((k_serve<NV, BPV>), dim3(s->ncu), dim3(kRenderLanes), render_lds_bytes(NV), st, dh, dd, dt, q);
 }
 
@@ -178,7 +201,7 @@ static hipError_t serve_enqueue(const ro_server *s, int h, hipStream_t st) {
 
 extern "C" ro_status ro_serve_query(uint32_t max_requests, uint32_t max_tiles, size_t *device_bytes) {
     RO_CHECK(device_bytes, RO_E_ARG, "null argument");
-    *device_bytes = 2 * serve_half_bytes(max_requests, max_tiles) + 512;
+    *device_bytes = 2 * serve_half_bytes(max_requests, max_tiles) + 1024;
     return RO_OK;
 }
 
@@ -192,6 +215,7 @@ extern "C" void ro_serve_destroy(ro_server *s) {
         if (s->stream[h]) (void)hipStreamDestroy(s->stream[h]);
     }
     if (s->host) (void)hipHostFree(s->host);
+    if (s->flags) (void)hipHostFree(s->flags);
     delete s;
 }
 
@@ -224,6 +248,19 @@ extern "C" ro_status ro_serve_create(ro_octree *t, uint32_t max_requests, uint32
         }
         s->host = (uint8_t *)h;
         memset(h, 0, 2 * s->half);
+        void *f = nullptr;
+        if ((e = hipHostMalloc(&f, 2 * sizeof(uint32_t) * max_requests, hipHostMallocMapped)) != hipSuccess) {
+            what = "hipHostMalloc (mapped)";
+            break;
+        }
+        s->flags = (uint32_t *)f;
+        memset(f, 0, 2 * sizeof(uint32_t) * max_requests);
+        void *fd = nullptr;
+        if ((e = hipHostGetDevicePointer(&fd, f, 0)) != hipSuccess) {
+            what = "hipHostGetDevicePointer";
+            break;
+        }
+        s->flags_dev = (uint32_t *)fd;
         for (int k = 0; k < 2 && e == hipSuccess; ++k) {
             e = hipStreamCreateWithFlags(&s->stream[k], hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev[k], hipEventDisableTiming);
@@ -284,6 +321,9 @@ extern "C" ro_status ro_serve_prepare(ro_server *s, uint32_t n, const ro_frame_d
     }
     hh->n_tiles = nt;
     hh->n_req = n;
+    hh->seq = (uint32_t)s->next_ticket;  // the ticket the next submission assigns
+    hh->done = serve_done(s, h);
+    hh->flags = s->flags_dev + (size_t)h * s->max_req;
     s->nv[h] = full_channels ? 16 : (maxvis <= 4 ? 4 : (maxvis <= 8 ? 8 : 16));
     s->ready = h;
     return RO_OK;
@@ -349,6 +389,21 @@ extern "C" ro_status ro_serve_poll(ro_server *s, uint64_t ticket, int32_t *done)
     }
     RO_HIP(e);
     *done = 1;
+    return RO_OK;
+}
+
+extern "C" ro_status ro_serve_request_done(ro_server *s, uint64_t ticket, uint32_t r, int32_t *done) {
+    RO_CHECK(s && done, RO_E_ARG, "null argument");
+    int h;
+    ro_status st = serve_ticket_half(s, ticket, &h);
+    if (st) return st;
+    RO_CHECK(r < s->max_req, RO_E_ARG, "request index %u out of range", r);
+    if (h < 0) {
+        *done = 1;
+        return RO_OK;
+    }
+    const volatile uint32_t *f = s->flags + (size_t)h * s->max_req;
+    *done = f[r] == (uint32_t)ticket ? 1 : 0;
     return RO_OK;
 }
 

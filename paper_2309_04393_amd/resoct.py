@@ -482,6 +482,7 @@ _sig("ro_serve_submit", c_i32, [c_vp, c_u32, _P(c_u64)])
 _sig("ro_serve_poll", c_i32, [c_vp, c_u64, _P(c_i32)])
 _sig("ro_serve_wait", c_i32, [c_vp, c_u64])
 _sig("ro_serve_work_items", c_i32, [c_i32, c_i32, _P(c_u32)])
+_sig("ro_serve_request_done", c_i32, [c_vp, c_u64, c_u32, _P(c_i32)])
 
 
 def serve_work_items(W: int, H: int) -> int:
@@ -537,3 +538,8 @@ class Server:
 
     def wait(self, ticket: int):
         _check(_lib.ro_serve_wait(self.h, ticket), "ro_serve_wait")
+
+    def request_done(self, ticket: int, r: int) -> bool:
+        d = c_i32()
+        _check(_lib.ro_serve_request_done(self.h, ticket, r, ctypes.byref(d)), "ro_serve_request_done")
+        return bool(d.value)

@@ -11,8 +11,10 @@ renders and the tail of one overlaps the head of the next on the device.
 With graph submission each half's device work (descriptor copy, queue reset,
 persistent kernel) is a captured graph replayed with new contents.
 
-Latency of a request = completion of its batch on the device (seen by
-polling) - its arrival.  The cache and octree are static while serving
+Latency of a request = its completion on the device (the kernel posts each
+request's completion to mapped host memory when its last pixels are
+written; the loop polls) - its arrival.  Within a batch the smallest
+requests come first.  The cache and octree are static while serving
 (every brick resident); streaming would be ordered between batches.
 """
 from __future__ import annotations
@@ -137,6 +139,9 @@ class ServingLoop:
         return batch
 
     def _submit(self, batch, now):
+        # smallest requests first: each request completes (and is reported)
+        # as soon as its own work items are done
+        batch = sorted(batch, key=lambda r: r.tiles)
         outs = [self.arena.view(r.mem[0], 4 * r.W * r.H) for r in batch]
         fds = [self.frame_desc(r, o) for r, o in zip(batch, outs)]
         for r, fd in zip(batch, fds):
@@ -173,15 +178,18 @@ class ServingLoop:
                 i += 1
                 progressed = True
             for b in list(inflight):
-                if self.server.poll(b.ticket):
-                    inflight.remove(b)
-                    tdone = clock() - t0
-                    for r in b.reqs:
-                        r.done = tdone
+                # requests complete one by one (flags posted by the kernel);
+                # the batch leaves the device when its kernel has ended
+                for idx, r in enumerate(b.reqs):
+                    if r.mem is not None and self.server.request_done(b.ticket, idx):
+                        r.done = clock() - t0
                         if on_done is not None:
                             on_done(r, self.arena.view(r.mem[0], 4 * r.W * r.H))
                         self.arena.free(*r.mem)
                         r.mem = None
+                        progressed = True
+                if all(r.mem is None for r in b.reqs) and self.server.poll(b.ticket):
+                    inflight.remove(b)
                     progressed = True
             if len(inflight) < 2 and queue:
                 batch = self._admit(queue, now)

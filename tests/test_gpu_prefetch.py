@@ -96,3 +96,45 @@ def test_rows_history_labels_candidates(cells):
     assert set(want) <= set(got) and set(got) - set(want) <= {int(p.ids[b]) for b in near}
     assert max(abs(got[i] - want[i]) for i in want) <= 1e-6
     _report("pf-candidates", n=len(got), near_threshold=len(near))
+
+
+def test_learned_policy_gains_over_plain_streaming():
+    """The predictor trained online along three camera paths, then both
+    policies on two held-out paths from an empty cache with the same upload
+    budget (4-channel 2048 x 2048 x 64 cells, 2 GiB cache, 1024 x 1024
+    views, 512 bricks per frame): the learned policy leaves fewer channel
+    samples without their desired brick (it only changes which bricks are
+    streamed)."""
+    from paper_2309_04393_amd.pipeline import GpuScene
+    from paper_2309_04393_amd.prefetch import BrickStore, run_path, save_state
+    from tests.helpers import leaf_grid
+    import bench
+    src = synth.config2_volume()
+    leaf = (16, 16, 4)
+    lg = leaf_grid(src.dims, leaf, 7)
+    scene = GpuScene(src, 32, leaf, 7, 27318, max_batch=512, start_level=2, set_metadata=False)
+    mx = src.leaf_max_all(leaf, lg)
+    for c in range(src.n_channels):
+        mm = np.zeros((mx.shape[1], 2), np.uint16)
+        mm[:, 1] = mx[c]
+        scene.set_metadata(c, mm)
+    store = BrickStore(scene)
+    empty = save_state(scene)
+    chans = [dict(ch, hi=src.n_levels - 1) for ch in bench.channels(src.n_channels, 2)]
+    net = resoct.Mlp()
+    net.set_weights(synth.mlp_init(7))
+    path = lambda s: synth.random_path(src.dims, src.spacing, s, 120)
+    for s in (1000, 1001, 1002):
+        run_path(scene, store, path(s), chans, 1024, 1024, 512, 0.5, "learned", net, empty)
+    res = []
+    for s in (1010, 1012):
+        _, p = run_path(scene, store, path(s), chans, 1024, 1024, 512, 0.5, "plain", None, empty)
+        _, q = run_path(scene, store, path(s), chans, 1024, 1024, 512, 0.5, "learned", net, empty)
+        res.append((p, q))
+        _report(f"pf-eval-{s}", plain_missing=round(p["mean_missing"], 4), learned_missing=round(q["mean_missing"], 4),
+                plain_converge=p["frames_to_converge"], learned_converge=q["frames_to_converge"],
+                plain_bytes=p["bytes_streamed"], learned_bytes=q["bytes_streamed"], extra=q["extra"],
+                precision=q["precision"])
+    plain = np.mean([p["mean_missing"] for p, _ in res])
+    learned = np.mean([q["mean_missing"] for _, q in res])
+    assert learned < plain, (plain, learned)

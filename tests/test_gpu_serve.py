@@ -121,7 +121,9 @@ def test_alone_equals_mix_equals_frame_kernel(scene):
         rig.stats.zero_()
         outs = [rig.out(k) for k in range(len(rig.reqs))]
         torch.cuda.synchronize()
-        srv.wait(srv.launch([rig.fd(k) for k in range(len(rig.reqs))], outs, graph=graph))
+        t = srv.launch([rig.fd(k) for k in range(len(rig.reqs))], outs, graph=graph)
+        srv.wait(t)
+        assert all(srv.request_done(t, k) for k in range(len(rig.reqs))), "completion flags not posted"
         st = rig.stats.cpu().numpy()
         for k in range(len(rig.reqs)):
             exact += _same(rig.image(k, outs[k]), ref[k], f"mix-{k}")
