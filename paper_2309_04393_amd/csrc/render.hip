@@ -169,6 +169,8 @@ ro_status build_render_args(ro_octree *tr, const ro_frame_desc *fd, float *rgba,
     A.nvis = fd->n_vis;
     A.ident = fd->n_vis == g.m && g.m % 4 == 0;
     for (int j = 0; j < fd->n_vis; ++j) A.ident = A.ident && fd->vis[j] == j;
+    A.uni = 1;
+    for (int j = 0; j < fd->n_vis; ++j) A.uni = A.uni && fd->lod_lo[j] == fd->lod_lo[0] && fd->lod_hi[j] == fd->lod_hi[0];
     for (int j = 0; j < fd->n_vis; ++j) {
         A.vis[j] = fd->vis[j];
         A.lo[j] = fd->lod_lo[j];

@@ -21,6 +21,7 @@ struct RenderArgs {
     float term;
     uint32_t frame, flags;
     int32_t ident;  // visible slot j shows channel j for every channel, and m % 4 == 0
+    int32_t uni;    // every visible channel has the same level range (lo[0], hi[0])
     // uniform tables copied to LDS by the workgroup
     int32_t vis[kMaxC], lo[kMaxC], hi[kMaxC];
     uint32_t W0[kMaxC], W1[kMaxC];
@@ -522,31 +523,55 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
             // samples (finest resident at or above the desired one).
             const uint16_t *lm = A.mask + (size_t)leaf * m;
             uint32_t look = 0;  // channels with a resident brick to look up
+            bool all_at = false;  // every non-empty channel resident at the common desired level
+            int lsu = 0;
+            if (NV >= 4 && A.ident && A.uni) {
+                // one desired level for every channel: AND the masks of all
+                // channels (two per word) and test its bit
+                lsu = min(max(lod, A.lo[0]), A.hi[0]);
+                uint32_t andm = 0xFFFFFFFFu;
 #pragma unroll
-            for (int g = 0; g < NV; g += kGroup) {
-                if (g >= nvis) break;
-                uint32_t mk[kGroup];
-                if (kGroup == 4 && A.ident) {
+                for (int g = 0; g < NV; g += 4) {
+                    if (g >= nvis) break;
                     const uint2 v = *(const uint2 *)(lm + g);
-                    mk[0] = v.x & 0xFFFFu;
-                    mk[kGroup > 1 ? 1 : 0] = v.x >> 16;
-                    mk[kGroup > 2 ? 2 : 0] = v.y & 0xFFFFu;
-                    mk[kGroup > 3 ? 3 : 0] = v.y >> 16;
-                } else {
-#pragma unroll
-                    for (int jj = 0; jj < kGroup; ++jj) mk[jj] = g + jj < nvis ? (uint32_t)lm[s_ch[g + jj].c] : 0u;
+                    andm &= v.x & v.y;
                 }
+                andm &= andm >> 16;
+                all_at = ((andm >> lsu) & 1u) != 0;
+            }
+            if (all_at) {
+                look = vismask & ~emask;
+                lvpack = 0;
 #pragma unroll
-                for (int jj = 0; jj < kGroup; ++jj) {
-                    const int j = g + jj;
-                    if (j < nvis && !((emask >> j) & 1u)) {
-                        const ChanLds ch = s_ch[j];
-                        const int ls = min(max(lod, ch.lo), ch.hi);
-                        const uint32_t mj = mk[jj] >> ls;
-                        if (!(mj & 1u)) missmask |= 1u << j;
-                        if (mj) {
-                            lvpack |= (uint64_t)(ls + __builtin_ctz(mj)) << (4 * j);
-                            look |= 1u << j;
+                for (int j = 0; j < NV; ++j)
+                    if ((look >> j) & 1u) lvpack |= (uint64_t)lsu << (4 * j);
+            } else {
+#pragma unroll
+                for (int g = 0; g < NV; g += kGroup) {
+                    if (g >= nvis) break;
+                    uint32_t mk[kGroup];
+                    if (kGroup == 4 && A.ident) {
+                        const uint2 v = *(const uint2 *)(lm + g);
+                        mk[0] = v.x & 0xFFFFu;
+                        mk[kGroup > 1 ? 1 : 0] = v.x >> 16;
+                        mk[kGroup > 2 ? 2 : 0] = v.y & 0xFFFFu;
+                        mk[kGroup > 3 ? 3 : 0] = v.y >> 16;
+                    } else {
+#pragma unroll
+                        for (int jj = 0; jj < kGroup; ++jj) mk[jj] = g + jj < nvis ? (uint32_t)lm[s_ch[g + jj].c] : 0u;
+                    }
+#pragma unroll
+                    for (int jj = 0; jj < kGroup; ++jj) {
+                        const int j = g + jj;
+                        if (j < nvis && !((emask >> j) & 1u)) {
+                            const ChanLds ch = s_ch[j];
+                            const int ls = min(max(lod, ch.lo), ch.hi);
+                            const uint32_t mj = mk[jj] >> ls;
+                            if (!(mj & 1u)) missmask |= 1u << j;
+                            if (mj) {
+                                lvpack |= (uint64_t)(ls + __builtin_ctz(mj)) << (4 * j);
+                                look |= 1u << j;
+                            }
                         }
                     }
                 }
@@ -557,11 +582,14 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
             // (the page table does not change during a frame).
             uint32_t key = kInvalid;
             if (look) {
-                const int lu0 = (int)((lvpack >> (4 * __builtin_ctz(look))) & 15u);
+                int lu0 = lsu;
                 bool uniform = true;
+                if (!all_at) {
+                    lu0 = (int)((lvpack >> (4 * __builtin_ctz(look))) & 15u);
 #pragma unroll
-                for (int j = 0; j < NV; ++j)
-                    if (((look >> j) & 1u) && (int)((lvpack >> (4 * j)) & 15u) != lu0) uniform = false;
+                    for (int j = 0; j < NV; ++j)
+                        if (((look >> j) & 1u) && (int)((lvpack >> (4 * j)) & 15u) != lu0) uniform = false;
+                }
                 if (uniform) {
                     const LevLds lv = s_lv[lu0];
                     key = brick_dense(lv, 0u, 0u, iu[0] >> field(lv.sh, 0), iu[1] >> field(lv.sh, 1),
@@ -570,39 +598,44 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 }
             }
             const uint32_t reuse = (key != kInvalid && key == last_key) ? have : 0u;
-            uint32_t nhave = 0;
+            uint32_t nhave = reuse & look;
+            // channels whose slot changes: looked up anew, or no longer sampled
+            if ((look & ~reuse) | (have & ~look)) {
+                nhave = 0;
 #pragma unroll
-            for (int g = 0; g < NV; g += kGroup) {
-                if (g >= nvis) break;
-                uint32_t ns[kGroup];
+                for (int g = 0; g < NV; g += kGroup) {
+                    if (g >= nvis) break;
+                    uint32_t ns[kGroup];
 #pragma unroll
-                for (int jj = 0; jj < kGroup; ++jj) {
-                    const int j = g + jj;
-                    ns[jj] = kInvalid;
-                    if ((look >> j) & 1u) {
-                        if ((reuse >> j) & 1u) {
-                            ns[jj] = slot[j];
-                        } else {
-                            const int lu = (int)((lvpack >> (4 * j)) & 15u);
-                            const LevLds lv = s_lv[lu];
-                            ns[jj] = A.pt[brick_dense(lv, (uint32_t)s_ch[j].c, A.per_channel, iu[0] >> field(lv.sh, 0),
-                                                      iu[1] >> field(lv.sh, 1), iu[2] >> field(lv.sh, 2))];
+                    for (int jj = 0; jj < kGroup; ++jj) {
+                        const int j = g + jj;
+                        ns[jj] = kInvalid;
+                        if ((look >> j) & 1u) {
+                            if ((reuse >> j) & 1u) {
+                                ns[jj] = slot[j];
+                            } else {
+                                const int lu = (int)((lvpack >> (4 * j)) & 15u);
+                                const LevLds lv = s_lv[lu];
+                                ns[jj] = A.pt[brick_dense(lv, (uint32_t)s_ch[j].c, A.per_channel,
+                                                          iu[0] >> field(lv.sh, 0), iu[1] >> field(lv.sh, 1),
+                                                          iu[2] >> field(lv.sh, 2))];
+                            }
                         }
                     }
-                }
 #pragma unroll
-                for (int jj = 0; jj < kGroup; ++jj) {
-                    const int j = g + jj;
-                    if (j >= nvis) break;
-                    if (ns[jj] == kInvalid) {
-                        lvpack &= ~((uint64_t)15u << (4 * j));
-                    } else {
-                        nhave |= 1u << j;
-                        if (ns[jj] != slot[j]) A.stamp[ns[jj]] = A.frame;
+                    for (int jj = 0; jj < kGroup; ++jj) {
+                        const int j = g + jj;
+                        if (j >= nvis) break;
+                        if (ns[jj] == kInvalid) {
+                            lvpack &= ~((uint64_t)15u << (4 * j));
+                        } else {
+                            nhave |= 1u << j;
+                            if (ns[jj] != slot[j]) A.stamp[ns[jj]] = A.frame;
+                        }
+                        slot[j] = ns[jj];
                     }
-                    slot[j] = ns[jj];
+                    asm volatile("" ::: "memory");
                 }
-                asm volatile("" ::: "memory");
             }
             have = nhave;
             last_key = key;
