@@ -49,6 +49,8 @@ struct RenderArgs {
 struct ChanLds {
     int c, lo, hi, nruns;
     float w0, iw;
+    uint32_t ehi;     // one zero-opacity run starting at raw value 0: its last raw value, else ~0
+    uint32_t single;  // same in every entry: every visible channel has such a run
 };
 
 struct LevLds {
@@ -262,6 +264,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     const int s0 = A.start_level;
     const bool noskip = (A.flags & RO_RENDER_NO_SKIP) != 0;
     const NodeLds leafl = s_nd[D];
+    const bool single = s_ch[0].single != 0;
     uint32_t st_samples = 0, st_reads = 0, st_miss = 0, st_visits = 0, st_nonempty = 0, st_iters = 0;
 
     // ---- per-ray state
@@ -482,10 +485,19 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 #pragma unroll
                             for (int jj = 0; jj < kGroup; ++jj) mm[jj] = g + jj < nvis ? nm[s_ch[g + jj].c] : 0u;
                         }
+                        if (single) {
+                            // one zero run [0, ehi] per channel: empty iff the maximum is within it
 #pragma unroll
-                        for (int jj = 0; jj < kGroup; ++jj) {
-                            const int j = g + jj;
-                            if (j < nvis && range_empty(mm[jj], s_runs + j * kMaxRuns, s_ch[j].nruns)) em |= 1u << j;
+                            for (int jj = 0; jj < kGroup; ++jj) {
+                                const int j = g + jj;
+                                if (j < nvis && (mm[jj] >> 16) <= s_ch[j].ehi) em |= 1u << j;
+                            }
+                        } else {
+#pragma unroll
+                            for (int jj = 0; jj < kGroup; ++jj) {
+                                const int j = g + jj;
+                                if (j < nvis && range_empty(mm[jj], s_runs + j * kMaxRuns, s_ch[j].nruns)) em |= 1u << j;
+                            }
                         }
                         asm volatile("" ::: "memory");
                     }
@@ -793,7 +805,16 @@ __device__ __forceinline__ void stage_frame(const RenderArgs &A, float4 *s_tf, C
         ch.w0 = A.w0[t];
         ch.iw = A.iw[t];
         ch.nruns = build_runs(s_tf + t * 256, A.W0[t], A.W1[t], s_runs + t * kMaxRuns);
+        const uint32_t r0 = s_runs[t * kMaxRuns];
+        ch.ehi = (ch.nruns == 1 && (r0 & 0xFFFFu) == 0) ? (r0 >> 16) : 0xFFFFFFFFu;
+        ch.single = 0;
         s_ch[t] = ch;
+    }
+    __syncthreads();
+    if (t < (unsigned)nvis) {
+        uint32_t all = 1;
+        for (int j = 0; j < nvis; ++j) all &= s_ch[j].ehi != 0xFFFFFFFFu ? 1u : 0u;
+        s_ch[t].single = all;
     }
     __syncthreads();
 
