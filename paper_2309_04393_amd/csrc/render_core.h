@@ -250,7 +250,15 @@ struct BlockQueue {
     }
 };
 
-template <int NV, int BPV, bool AOV, class Source>
+// Slot bytes of a brick of edge e (halo included): rounded up to 256 bytes,
+// as the cache lays out its slots.
+__host__ __device__ constexpr size_t slot_bytes(int e, int bpv) {
+    return ((size_t)e * e * e * bpv + 255) / 256 * 256;
+}
+
+// EC: the brick edge with halo known at compile time (0: read from A).  A
+// constant edge turns the four gather offsets into instruction immediates.
+template <int NV, int BPV, bool AOV, int EC, class Source>
 __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, const float4 *s_tf,
                                             const ChanLds *s_ch, const uint32_t *s_runs, const LevLds *s_lv,
                                             const NodeLds *s_nd, uint32_t stats[6], LdsSlots slot) {
@@ -665,7 +673,8 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         int lprev = -1;
         uint32_t idx = 0;
         float fr0 = 0.0f, fr1 = 0.0f, fr2 = 0.0f;
-        const uint32_t E = (uint32_t)A.E;
+        const uint32_t E = EC ? (uint32_t)EC : (uint32_t)A.E;
+        const size_t stride = EC ? slot_bytes(EC, BPV) : (size_t)A.slot_stride;
 #pragma unroll
         for (int g = 0; g < NV; g += kGroup) {
             if (g >= nvis) break;
@@ -702,7 +711,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 fq[jj][2] = fr2;
                 // a channel without a slot reads offset 0 of slot 0 (always
                 // inside the pool) and its result is discarded
-                const uint8_t *base = A.slots + (ok[jj] ? (size_t)slot[j] * A.slot_stride + (size_t)idx * BPV : 0);
+                const uint8_t *base = A.slots + (ok[jj] ? (size_t)slot[j] * stride + (size_t)idx * BPV : 0);
                 w[jj][0] = vpair<BPV>(base);
                 w[jj][1] = vpair<BPV>(base + (size_t)E * BPV);
                 w[jj][2] = vpair<BPV>(base + (size_t)E * E * BPV);

@@ -49,7 +49,7 @@ __host__ __device__ inline uint32_t serve_segments(int W, int H) {
 // if it changed, and its waves take the segment's blocks from an LDS counter
 // one at a time, so waves that finish early take more blocks; the workgroup
 // waits for its slowest wave only once per segment.
-template <int NV, int BPV>
+template <int NV, int BPV, int EC>
 __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(kRenderLanes / 256)))
     k_serve(const ServeHeader *__restrict__ hdr, const RenderArgs *__restrict__ descs,
             const uint32_t *__restrict__ segs, uint32_t *__restrict__ queue) {
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
         q.min_idle = 64;
         uint32_t st[6] = {0, 0, 0, 0, 0, 0};
         const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
-        render_rays<NV, BPV, false>(sA, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
+        render_rays<NV, BPV, false, EC>(sA, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
         if (sA.stats) {
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
@@ -168,21 +168,39 @@ static inline uint32_t *serve_done(const ro_server *s, int h) {
     return (uint32_t *)(s->dev + 2 * s->half + 512 + 256 * (size_t)h);
 }
 
-template <int NV, int BPV>
-static hipError_t serve_attr() {
-    return hipFuncSetAttribute((const void *)k_serve<NV, BPV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+template <int NV, int BPV, int EC>
+static hipError_t serve_attr1() {
+    return hipFuncSetAttribute((const void *)k_serve<NV, BPV, EC>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)render_lds_bytes(NV));
 }
 
 template <int NV, int BPV>
-static void serve_launch_t(const ro_server *s, int h, hipStream_t st) {
+static hipError_t serve_attr() {
+    hipError_t e = serve_attr1<NV, BPV, 0>();
+    if (e == hipSuccess) e = serve_attr1<NV, BPV, 18>();
+    if (e == hipSuccess) e = serve_attr1<NV, BPV, 34>();
+    return e;
+}
+
+template <int NV, int BPV, int EC>
+static void serve_launch_e(const ro_server *s, int h, hipStream_t st) {
     const uint8_t *d = s->dev + (size_t)h * s->half;
     const ServeHeader *dh = (const ServeHeader *)d;
     const RenderArgs *dd = (const RenderArgs *)(d + sizeof(ServeHeader));
     const uint32_t *dt = (const uint32_t *)(d + sizeof(ServeHeader) + (size_t)s->max_req * sizeof(RenderArgs));
     uint32_t *q = serve_queue(s, h);
     hipLaunchKernelGGL(k_serve_reset, dim3(1), dim3(64), 0, st, q, serve_done(s, h), s->max_req);
-    hipLaunchKernelGGL((k_serve<NV, BPV>), dim3(s->ncu), dim3(kRenderLanes), render_lds_bytes(NV), st, dh, dd, dt, q);
+    hipLaunchKernelGGL((k_serve<NV, BPV, EC>), dim3(s->ncu), dim3(kRenderLanes), render_lds_bytes(NV), st, dh, dd, dt,
+                       q);
+}
+
+// compile-time brick edge for 32^3 and 16^3 bricks (see the frame kernel)
+template <int NV, int BPV>
+static void serve_launch_t(const ro_server *s, int h, hipStream_t st) {
+    const int E = s->tree->cache->vol->g.E;
+    if (E == 34) serve_launch_e<NV, BPV, 34>(s, h, st);
+    else if (E == 18) serve_launch_e<NV, BPV, 18>(s, h, st);
+    else serve_launch_e<NV, BPV, 0>(s, h, st);
 }
 
 // Device work of one submission from half h: copy, queue reset, kernel.
