@@ -37,6 +37,13 @@ namespace ro {
 #define RO_MIN_IDLE 64
 #endif
 
+#ifndef RO_QUEUES
+#define RO_QUEUES 8
+#endif
+#ifndef RO_CHUNK
+#define RO_CHUNK 64
+#endif
+
 // Persistent grid (one workgroup per CU) whose waves take 8 x 8-pixel blocks
 // from a device counter independently of each other, so a CU never waits
 // for the slowest wave of a workgroup before taking new work.
@@ -56,6 +63,8 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
     q.n_blocks = n_blocks;
     q.offset = 0;
     q.tiles_x = tiles_x;
+    q.n_queues = RO_QUEUES;
+    q.chunk = RO_CHUNK;
     q.W = A.W;
     q.H = A.H;
     q.min_idle = RO_MIN_IDLE;
@@ -218,7 +227,8 @@ ro_status render_device(ro_octree *tr, const ro_frame_desc *fd, float *rgba, hip
     // memset
     Q.counter = (uint32_t *)((uint8_t *)tr->b.scratch + tr->scratch_bytes - 256);
     Q.grid = dim3((unsigned)(ncu > 0 ? ncu : 256));
-    st = launch_fill_u32(Q.counter, 1, 0u, s);
+    static_assert(RO_QUEUES * kQueueStride * 4 <= 256, "queue counters exceed the scratch tail");
+    st = launch_fill_u32(Q.counter, (uint64_t)RO_QUEUES * kQueueStride, 0u, s);
     if (st) return st;
     const bool aov = (fd->flags & RO_RENDER_AOV) != 0;
     RO_HIP(g.bpv == 1 ? launch_bpv<1>(A, aov, Q, s) : launch_bpv<2>(A, aov, Q, s));

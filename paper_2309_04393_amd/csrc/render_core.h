@@ -178,27 +178,53 @@ struct OnePixel {
     __device__ __forceinline__ bool more() const { return false; }
 };
 
-// BlockQueue: waves take 8 x 8-pixel blocks from a device counter (blocks of
-// a 32 x 32 tile are consecutive, tiles in raster order), so the waves of
-// all CUs sweep the image together and share the Infinity Cache; splitting
-// the blocks into one range per XCD measured 4 % slower.  Lanes whose ray
-// ended take the next pixels of the wave's block, in lane order of a ballot
-// of the idle lanes (prefix ranks), once at least min_idle lanes are idle.
-// Counter reads and block state are wave-uniform.
+// BlockQueue: waves take 8 x 8-pixel blocks from device counters (blocks of
+// a 32 x 32 tile are consecutive, tiles in raster order).  With n_queues = 1
+// one counter hands out the blocks in order.  With n_queues > 1 the blocks
+// are dealt in chunks of `chunk` consecutive blocks, chunk c to queue
+// c mod n_queues; a workgroup starts on queue (workgroup index mod
+// n_queues), which with workgroups dealt to the XCDs in turn is its XCD's,
+// and takes from the next queues once its own is used up.  The XCDs then
+// work on separate neighbouring chunks (their L2s hold different lines)
+// while all of them still sweep the image together (the Infinity Cache is
+// shared).  Lanes whose ray ended take the next pixels of the wave's block,
+// in lane order of a ballot of the idle lanes (prefix ranks), once at least
+// min_idle lanes are idle.  Counter reads and block state are wave-uniform.
+constexpr int kQueueStride = 8;  // words between queue counters (32 bytes)
 struct BlockQueue {
     static constexpr bool kRefill = true;
-    uint32_t *counter;  // zero at launch (device or LDS word)
+    uint32_t *counter;  // n_queues counters kQueueStride words apart, zero at launch (device or LDS)
     uint32_t n_blocks;  // blocks this queue hands out: offset .. offset + n_blocks - 1
     uint32_t offset, tiles_x;
+    uint32_t n_queues, chunk;
     int W, H;
     int min_idle;     // refill when at least this many lanes are idle
     uint32_t block;   // current block (wave-uniform)
     uint32_t used;    // its pixels handed out
     bool exhausted;
+    uint32_t q, tried;  // current queue, queues found used up (wave-uniform)
 
     __device__ __forceinline__ uint32_t pop() {
-        uint32_t b = 0;
-        if ((threadIdx.x & 63) == 0) b = atomicAdd(counter, 1u);
+        uint32_t b = n_blocks;
+        if ((threadIdx.x & 63) == 0) {
+            if (n_queues == 1) {
+                b = atomicAdd(counter, 1u);
+            } else {
+                while (tried < n_queues) {
+                    const uint32_t i = atomicAdd(counter + q * kQueueStride, 1u);
+                    const uint64_t c = (uint64_t)(i / chunk) * n_queues + q;
+                    const uint64_t bb = c * chunk + i % chunk;
+                    if (bb < n_blocks) {
+                        b = (uint32_t)bb;
+                        break;
+                    }
+                    q = (q + 1) % n_queues;
+                    ++tried;
+                }
+            }
+        }
+        q = (uint32_t)__shfl((int)q, 0, 64);
+        tried = (uint32_t)__shfl((int)tried, 0, 64);
         return (uint32_t)__shfl((int)b, 0, 64);
     }
     __device__ __forceinline__ void pixel(uint32_t b, uint32_t i, int &x, int &y, bool &v) const {
@@ -210,6 +236,8 @@ struct BlockQueue {
     }
     __device__ __forceinline__ bool more() const { return !exhausted; }
     __device__ __forceinline__ bool first(int &x, int &y, bool &v) {
+        q = blockIdx.x % n_queues;
+        tried = 0;
         block = pop();
         used = 64;
         exhausted = block >= n_blocks;

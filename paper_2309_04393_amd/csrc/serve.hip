@@ -87,6 +87,8 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
         q.n_blocks = min(kSegBlocks, n_blk - first);
         q.offset = first;
         q.tiles_x = tiles_x;
+        q.n_queues = 1;
+        q.chunk = 1;
         q.W = sA.W;
         q.H = sA.H;
         q.min_idle = 64;
