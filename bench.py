@@ -433,7 +433,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="cfg3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile", type=int, default=192)
+    ap.add_argument("--tile", type=int, default=384,
+                    help="edge of the centre window the oracle renders for the CPU baseline and the parity check")
     ap.add_argument("--serve", type=float, default=10.0, metavar="SECONDS",
                     help="seconds of the serving measurement after the frame measurement (0: skip)")
     ap.add_argument("--serve-only", action="store_true", help="only the serving measurement")

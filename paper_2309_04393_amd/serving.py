@@ -204,16 +204,21 @@ class ServingLoop:
 
 def latency_summary(trace, t_from=0.0):
     """Latency percentiles over the requests arriving from t_from on; an
-    unfinished request counts as infinitely late."""
+    unfinished request counts as infinitely late (p50_ms / p99_ms are None
+    when that percentile is unbounded).  The *_completed_ms figures are over
+    the finished requests only."""
     lat = np.array([r.done - r.arrival for r in trace if r.arrival >= t_from])
     if not len(lat):
         return dict(n=0)
     fin = np.isfinite(lat)
     lat = np.where(fin, lat, np.inf)
     pct = lambda q: float(np.percentile(lat, q) * 1e3) if np.isfinite(np.percentile(lat, q)) else None
+    done = lat[fin]
     return dict(n=int(len(lat)), completed=int(fin.sum()), p50_ms=pct(50), p99_ms=pct(99),
-                mean_ms=float(lat[fin].mean() * 1e3) if fin.any() else None,
-                max_ms=float(lat[fin].max() * 1e3) if fin.any() else None)
+                mean_ms=float(done.mean() * 1e3) if fin.any() else None,
+                max_ms=float(done.max() * 1e3) if fin.any() else None,
+                p50_completed_ms=float(np.percentile(done, 50) * 1e3) if fin.any() else None,
+                p99_completed_ms=float(np.percentile(done, 99) * 1e3) if fin.any() else None)
 
 
 VIEWPORTS = ((256, 256), (512, 512), (1024, 1024), (1920, 1080))
