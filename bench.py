@@ -234,9 +234,20 @@ def cpu_baseline(cfg, cams, chans, f, step, tile):
     dt = time.perf_counter() - t
     assert not np.isnan(r["rgba"]).any(), "oracle sampled outside the materialised window"
     s = r["stats"]["samples"]
+    # one host thread on a quarter-edge window at the same centre
+    t1 = max(tile // 4, 8)
+    x1, y1 = (W - t1) // 2, (H - t1) // 2
+    V1, lv1, bx1, lm1, fr1 = oracle_window(cfg, cams[f], W, H, x1, y1, t1, step, chans)
+    t = time.perf_counter()
+    r1 = oracle.render(V1, lv1, res, lm1, fr1, 1, n_threads=1, boxes=bx1)
+    dt1 = time.perf_counter() - t
+    s1 = r1["stats"]["samples"]
     return dict(value=s / dt, unit="samples/s", cores=threads, kind="oracle",
                 sample=f"{tile}x{tile}-pixel window at the centre of timed frame {f}, all bricks resident, "
-                       f"{s} ray samples x {len(chans)} channels in {dt:.1f} s"), r, (x0, y0)
+                       f"{s} ray samples x {len(chans)} channels in {dt:.1f} s",
+                single_core_value=s1 / dt1,
+                single_core_sample=f"{t1}x{t1}-pixel window at the same centre, one thread, {s1} ray samples "
+                                   f"in {dt1:.1f} s"), r, (x0, y0)
 
 
 def sub_camera(cam, W, H, x0, y0, n):
@@ -275,6 +286,62 @@ def leaf_mm_all(cfg):
         mm[:, :, 1] = mx
         _LM[key] = mm
     return _LM[key]
+
+
+def streaming_bench(scene, fl, cams, f_req, f_up, U, mm0):
+    """Timing of the streaming steps on the paper-scale scene (after the
+    timed frames): request compaction (readback of the dense counters after
+    rendering the zoomed-out frame f_req, which misses many bricks), the
+    upload of the U most requested bricks (slot choice, LRU eviction,
+    scatter, page tables), the residency update of those bricks, the
+    from-scratch residency rebuild and the metadata reduction of one
+    channel.  GPU time from HIP events on the library's stream (torch's
+    current stream); algorithmic bytes per call as stated per entry."""
+    import torch
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        r = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return r, a.elapsed_time(b)
+
+    def entry(ms, nbytes, **kw):
+        gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None
+        return dict(ms=ms, alg_bytes=int(nbytes), achieved_GBs=gbs,
+                    frac_hbm_peak=gbs / HBM_PEAK_GBS if gbs is not None else None, **kw)
+
+    c = scene.cache
+    out = {"workload": "16ch-8192x8192x192-u16, 218551 slots, state after the timed frames",
+           "request_frame": f_req, "upload_frame": f_up}
+    fl.render(f_req)
+    (ids, cnt, nu, tot), ms = timed(lambda: c.read_requests(1 << 22))
+    out["a8_request_compaction"] = entry(ms, 4 * c.n_bricks + 12 * nu, bricks_scanned=c.n_bricks,
+                                         distinct_requested=nu, missing_samples=tot,
+                                         note="4 B per counter read + (ID, count) out + counter cleared per "
+                                              "requested brick; includes the host readback")
+    order = np.lexsort((ids, -cnt.astype(np.int64)))
+    up = ids[order][:U]
+    staged = scene.stage(up)
+    flags, ms = timed(lambda: c.stream_bricks(f_up, up, staged))
+    n_in = int((flags == 1).sum())
+    out["a9_upload"] = entry(ms, 2 * len(up) * c.slot_stride + 8 * c.n_slots, bricks=len(up), inserted=n_in,
+                             note="staging read + slot write per brick, (stamp, sequence) of every slot "
+                                  "once; includes the LRU selection and the host flags readback")
+    _, ms = timed(lambda: scene.tree.update_residency())
+    out["a10_residency_update"] = dict(ms=ms, dirty_bricks=2 * n_in)
+    _, ms = timed(lambda: scene.tree.rebuild_residency())
+    m = scene.vol.n_channels
+    out["a10_residency_rebuild"] = entry(ms, 2 * scene.tree.n_nodes * m + 4 * c.n_bricks,
+                                         note="every node mask written once, every page-table entry read once")
+    t = torch.from_numpy(np.ascontiguousarray(mm0, dtype=np.uint16).reshape(-1).view(np.int16)).to("cuda") \
+        .view(torch.uint16)
+    _, ms = timed(lambda: scene.tree.set_leaf_metadata(0, t))
+    out["a11_metadata_one_channel"] = entry(ms, 4 * scene.tree.n_leaves + 4 * scene.tree.n_nodes,
+                                            note="leaf (min, max) read + one metadata word written per node")
+    return out
 
 
 def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True, max_batch=64):
@@ -441,6 +508,7 @@ def main():
     ap.add_argument("--rate", type=float, default=400.0, help="serving arrival rate, requests/s")
     ap.add_argument("--serve-max-batch", type=int, default=64, help="requests per serving batch at most")
     ap.add_argument("--no-prefetch", action="store_true", help="skip the learned-prefetcher evaluation")
+    ap.add_argument("--no-streaming", action="store_true", help="skip the timing of the streaming steps")
     ap.add_argument("--prefetch-only", action="store_true",
                     help="only the learned-prefetcher evaluation (10 training, 5 held-out paths)")
     ap.add_argument("--pf-lr", type=float, default=3e-3)
@@ -593,6 +661,10 @@ def main():
                              "ambiguous_frac": float(1.0 - ok.mean())}
         except Exception as e:  # reported, not fatal
             out["cpu_baseline"] = {"error": repr(e)}
+    # after the parity window, which reads the last timed frame's image
+    if not args.no_streaming:
+        out["streaming"] = streaming_bench(scene, fl, cams, f_req=max(f0 - 60, 0), f_up=f0 + K, U=cfg["U"],
+                                           mm0=mm[0])
     if args.serve > 0 or not args.no_prefetch:
         del fl, store, scene
         torch.cuda.empty_cache()
