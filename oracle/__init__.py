@@ -50,7 +50,7 @@ class Frame(ctypes.Structure):
                 ("vis", ctypes.c_int * MAXC), ("lod_lo", ctypes.c_int * MAXC),
                 ("lod_hi", ctypes.c_int * MAXC), ("W0", ctypes.c_uint32 * MAXC),
                 ("W1", ctypes.c_uint32 * MAXC), ("tf", ctypes.c_void_p * MAXC),
-                ("term_alpha", ctypes.c_double), ("term_margin", ctypes.c_double)]
+                ("term_alpha", ctypes.c_double), ("term_margin", ctypes.c_double), ("adaptive", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -172,7 +172,7 @@ def tf_empty(mn, mx, W0, W1, tf) -> bool:
 
 
 def make_frame(cam: dict, W, H, delta, channels: list, term_alpha=0.99, lod_bias=1.0,
-               term_margin=1e-5):
+               term_margin=1e-5, adaptive=False):
     """channels: list of dicts {c, lo, hi, W0, W1, tf (256x4 float32)} in
     visible-slot order.  Returns (Frame, keepalive)."""
     fr = Frame()
@@ -185,6 +185,7 @@ def make_frame(cam: dict, W, H, delta, channels: list, term_alpha=0.99, lod_bias
     fr.W, fr.H = W, H
     fr.delta, fr.lod_bias, fr.term_alpha = delta, lod_bias, term_alpha
     fr.term_margin = term_margin
+    fr.adaptive = 1 if adaptive else 0
     fr.nvis = len(channels)
     keep = []
     for j, ch in enumerate(channels):

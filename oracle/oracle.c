@@ -344,6 +344,7 @@ typedef struct {
     const float *tf[OR_MAXC]; /* 256 x RGBA per visible slot */
     double term_alpha;
     double term_margin; /* |A - term_alpha| below this marks an ambiguous termination */
+    int adaptive;       /* LOD-adaptive step (Sec. 6.1, the sampling distance grows with the level) */
 } or_frame;
 
 /* Level data: lvl[c * L + l] points to the level's array [z][y][x]
@@ -527,7 +528,9 @@ typedef struct {
  *   amb_counts[dense]  requests of samples after an ambiguous termination
  *   amb_used[slot]     slots read by samples after an ambiguous termination
  * Every pixel's ray samples t_k = k delta, k = 0, 1, ...; samples outside
- * [0, dims) are void.  Early termination when A >= term_alpha. */
+ * [0, dims) are void.  Early termination when A >= term_alpha.  With
+ * Fr->adaptive only the samples on the grid of their level band are taken
+ * (see the step range below). */
 int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, const or_source *src,
               const int32_t *res_slot, const uint16_t *leaf_mm, const or_frame *Fr, int row0,
               int row1, double *rgba, uint32_t *counts, uint8_t *used, uint32_t *aov,
@@ -547,6 +550,17 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
         double s_l = G.f[l][0] * V->spacing[0];
         Dl[l] = s_l / (Fr->lod_bias * pix);
         if (Fr->proj == 0 && Fr->lod_bias * pix >= s_l) n_ortho++;
+    }
+    /* LOD-adaptive step: the sampling distance follows the finest desired
+     * level over the visible channels, min_c clamp(l*, lo_c, hi_c) =
+     * clamp(l*, min_c lo_c, min_c hi_c); a sample k is taken only when k is
+     * a multiple of that level's x factor r, and its mixed opacity is
+     * corrected to 1 - (1 - alpha)^r (the premultiplied colour scaled with
+     * it), so a coarse band keeps the opacity per unit length. */
+    int step_lo = OR_MAXL, step_hi = OR_MAXL;
+    for (int jv = 0; jv < Fr->nvis; ++jv) {
+        if (Fr->lod_lo[jv] < step_lo) step_lo = Fr->lod_lo[jv];
+        if (Fr->lod_hi[jv] < step_hi) step_hi = Fr->lod_hi[jv];
     }
     long long st_s = 0, st_cs = 0, st_m = 0, st_as = 0, st_ap = 0;
     if (!lvl && !(src && src->fetch)) return -1;
@@ -593,15 +607,30 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
                     int lc[3];
                     for (int a = 0; a < 3; ++a) lc[a] = iu[a] / V->leaf[a];
                     long long leaf = ((long long)lc[2] * T.n[Dp][1] + lc[1]) * T.n[Dp][0] + lc[0];
-                    int nlev;
+                    int nlev, lamb = 0;
                     if (Fr->proj == 0) nlev = n_ortho;
                     else {
                         nlev = 0;
                         for (int l = 1; l < L; ++l) {
                             if (t >= Dl[l]) nlev++;
-                            if (fabs(t - Dl[l]) <= 1e-9 * Dl[l]) samb = 1;
+                            if (fabs(t - Dl[l]) <= 1e-9 * Dl[l]) lamb = 1;
                         }
                     }
+                    int rstep = 1;
+                    if (Fr->adaptive) {
+                        int ls = nlev;
+                        if (ls < step_lo) ls = step_lo;
+                        if (ls > step_hi) ls = step_hi;
+                        if (ls > L - 1) ls = L - 1;
+                        rstep = G.f[ls][0];
+                        if (k % rstep != 0) {
+                            /* not on this band's grid; a level decision close to
+                             * its threshold may take it on another renderer */
+                            if (lamb && !tol) { pamb = 1; st_as++; }
+                            continue;
+                        }
+                    }
+                    samb |= lamb;
                     if (samb && !tol) { pamb = 1; st_as++; }
                     if (!shadow) st_s++;
                     double prod = 1.0, sa = 0.0, srgb[3] = {0, 0, 0};
@@ -662,6 +691,7 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
                     /* mix: alpha_s = 1 - prod(1 - alpha_c);
                      * C_s = alpha_s * sum(alpha_c rgb_c) / sum(alpha_c) */
                     double as = 1.0 - prod;
+                    if (rstep > 1) as = 1.0 - pow(prod, (double)rstep);
                     double Cs[3] = {0, 0, 0};
                     if (sa > 0.0)
                         for (int k2 = 0; k2 < 3; ++k2) Cs[k2] = as * srgb[k2] / sa;

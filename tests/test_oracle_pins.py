@@ -179,6 +179,66 @@ def test_constant_volume_closed_form(a):
     assert (r["aov"][..., 0] == n).all()
 
 
+@pytest.mark.parametrize("a", [0.05, 0.2, 0.5])
+def test_adaptive_step_constant_volume_closed_form(a):
+    """LOD-adaptive step (Sec. 6.1: the sampling distance may grow with the
+    level): with the level fixed at 1 (x factor r = 2) only the samples
+    k = 2, 4, .., 32 are taken, each with opacity 1 - (1-a)^2, so
+    A = 1 - (1-a)^(2n) with n = min(16, ceil(ln 0.01 / (2 ln(1-a))))."""
+    l0 = np.full((16, 16, 16), 128, np.uint8)
+    l1 = np.full((8, 8, 8), 128, np.uint8)
+    tf = _const_tf((0.2, 0.4, 0.6), a)
+    af = float(np.float32(a))
+    ch = [dict(c=0, lo=1, hi=1, W0=0, W1=255 * 256, tf=tf)]
+    V = _scene_V([[l0, l1]], 8, 8, (4, 4, 4), 2)
+    cam = synth.camera_ortho_axis((16, 16), 16, 16)
+    fr, keep = oracle.make_frame(cam, 16, 16, 0.5, ch, term_alpha=0.99, adaptive=True)
+    r = oracle.render(V, [[l0, l1]], _all_resident(V), _leaf_mm_full(V, [[l0, l1]]), fr,
+                      oracle.brick_count(V), aov=True)
+    n = min(16, math.ceil(math.log(0.01) / (2 * math.log(1 - af))))
+    A = 1 - (1 - af) ** (2 * n)
+    rgb = np.array([np.float32(0.2), np.float32(0.4), np.float32(0.6)], dtype=np.float64)
+    assert np.allclose(r["rgba"][..., 3], A, atol=1e-12, rtol=0)
+    assert np.allclose(r["rgba"][..., :3], rgb * A, atol=1e-12, rtol=0)
+    assert (r["aov"][..., 1] == n).all() and (r["aov"][..., 0] == 0).all()
+
+
+def test_adaptive_step_reduces_to_plain_rendering():
+    """With every channel's level fixed at l (x factor r) and a transfer
+    function of constant opacity a, the adaptive renderer at step d equals
+    the plain renderer at step r d with the opacity a' = 1 - (1-a)^r in the
+    table (same sample positions, same per-sample colour and opacity); with
+    the finest level (r = 1) it equals the plain renderer at step d."""
+    vol = synth.BlobVolume((32, 32, 32), n_channels=1, bits=8, n_levels=3, seed=21)
+    V = oracle.make_volume((32, 32, 32), (1, 1, 1), 1, 8, 8, 3, (4, 4, 4), 3)
+    lm = np.stack([vol.leaf_minmax(0, (4, 4, 4), (8, 8, 8))])
+    cam = synth.camera_persp((48.0, 40.0, 70.0), (16.0, 16.0, 16.0), (0.0, 1.0, 0.0), 40.0, 1.0)
+    a = 0.15
+    rgb_tab = synth.tf_hue(0.6, 1.0).astype(np.float32)
+    tf = rgb_tab.copy()
+    tf[:, 3] = a
+    for lvl in (1, 2):
+        r_fac = 2 ** lvl
+        ch = [dict(c=0, lo=lvl, hi=lvl, W0=12 * 256, W1=255 * 256, tf=tf)]
+        fr, keep = oracle.make_frame(cam, 40, 40, 0.5, ch, adaptive=True)
+        ra = oracle.render(V, vol.levels, _all_resident(V), lm, fr, oracle.brick_count(V))
+        tf2 = tf.copy()
+        tf2[:, 3] = 1.0 - (1.0 - np.float64(np.float32(a))) ** r_fac
+        ch2 = [dict(ch[0], tf=tf2)]
+        fr2, keep2 = oracle.make_frame(cam, 40, 40, 0.5 * r_fac, ch2)
+        rp = oracle.render(V, vol.levels, _all_resident(V), lm, fr2, oracle.brick_count(V))
+        # the corrected table entry is rounded to float32 on the plain side
+        assert np.abs(ra["rgba"] - rp["rgba"]).max() < 1e-6
+        assert ra["rgba"][..., 3].max() > 0.1
+        assert ra["stats"]["samples"] == rp["stats"]["samples"]
+    ch = [dict(c=0, lo=0, hi=0, W0=12 * 256, W1=255 * 256, tf=synth.tf_ramp())]
+    fr, keep = oracle.make_frame(cam, 40, 40, 0.5, ch, adaptive=True)
+    fr0, keep0 = oracle.make_frame(cam, 40, 40, 0.5, ch)
+    ra = oracle.render(V, vol.levels, _all_resident(V), lm, fr, oracle.brick_count(V))
+    r0 = oracle.render(V, vol.levels, _all_resident(V), lm, fr0, oracle.brick_count(V))
+    assert np.array_equal(ra["rgba"], r0["rgba"]) and np.array_equal(ra["counts"], r0["counts"])
+
+
 def test_single_channel_mix_is_identity_and_duplicates_combine():
     """R24 mix: one channel passes (rgb, alpha) through; two identical
     channels give alpha_s = 1 - (1 - alpha)^2 with the same colour."""
