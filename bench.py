@@ -344,6 +344,47 @@ def streaming_bench(scene, fl, cams, f_req, f_up, U, mm0):
     return out
 
 
+def adaptive_bench(scene, fl, frames, reps=3):
+    """The LOD-adaptive step (RO_RENDER_ADAPTIVE_STEP) on zoomed-out frames of
+    the fly-through, where samples fall in coarse level bands: each frame's
+    working set is made resident (bulk uploads of its requests), then the
+    frame is rendered with the plain and with the adaptive step; mean kernel
+    time from HIP events and the ray samples evaluated."""
+    import torch
+    from paper_2309_04393_amd import resoct
+    out = {}
+    for f in frames:
+        for _ in range(4):
+            fl.render(f)
+            ids, cnt, nu, tot = scene.cache.read_requests(1 << 22)
+            if nu == 0:
+                break
+            scene.upload(f, ids)
+            scene.tree.update_residency()
+        row = {}
+        for name, flags in (("plain", 0), ("adaptive", resoct.RENDER_ADAPTIVE_STEP)):
+            ms = []
+            for _ in range(reps):
+                fl.stats.zero_()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                a.record()
+                scene.render(f, fl.cams[f], fl.W, fl.H, fl.step, fl.chans, tf_dev=fl.tf, out=fl.out,
+                             stats=fl.stats, flags=flags)
+                b.record()
+                torch.cuda.synchronize()
+                ms.append(a.elapsed_time(b))
+            st = fl.stats.cpu().numpy()
+            _, _, nu2, tot2 = scene.cache.read_requests(1 << 22)
+            row[name] = dict(ms=float(np.mean(ms)), samples=int(st[0]), channel_samples=int(st[1]),
+                             missing_samples=int(tot2), leaf_visits=int(st[3]),
+                             lane_busy=float(st[0]) / max(float(st[5]), 1.0))
+        row["speedup"] = row["plain"]["ms"] / row["adaptive"]["ms"]
+        out[str(f)] = row
+        log(f"adaptive step, frame {f}: {row}")
+    return out
+
+
 def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True, max_batch=64):
     """Serving on the 16-channel 2048 x 2048 x 64 cell volume, every brick
     resident in a 24 GiB cache: 64 clients, Poisson arrivals at `rate`
@@ -509,6 +550,8 @@ def main():
     ap.add_argument("--serve-max-batch", type=int, default=64, help="requests per serving batch at most")
     ap.add_argument("--no-prefetch", action="store_true", help="skip the learned-prefetcher evaluation")
     ap.add_argument("--no-streaming", action="store_true", help="skip the timing of the streaming steps")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the LOD-adaptive step measurement on zoomed-out frames")
     ap.add_argument("--prefetch-only", action="store_true",
                     help="only the learned-prefetcher evaluation (10 training, 5 held-out paths)")
     ap.add_argument("--pf-lr", type=float, default=3e-3)
@@ -665,6 +708,8 @@ def main():
     if not args.no_streaming:
         out["streaming"] = streaming_bench(scene, fl, cams, f_req=max(f0 - 60, 0), f_up=f0 + K, U=cfg["U"],
                                            mm0=mm[0])
+    if not args.no_adaptive:
+        out["adaptive_step"] = adaptive_bench(scene, fl, (0, 40, 80))
     if args.serve > 0 or not args.no_prefetch:
         del fl, store, scene
         torch.cuda.empty_cache()

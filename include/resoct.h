@@ -243,6 +243,7 @@ ro_status ro_rebuild_residency(ro_octree *t, void *stream);
 
 #define RO_RENDER_NO_SKIP 1u /* evaluate every sample (results are identical) */
 #define RO_RENDER_AOV 2u     /* write per-pixel per-level sample counts to aov_dev */
+#define RO_RENDER_ADAPTIVE_STEP 4u /* LOD-adaptive sampling distance (see below) */
 
 /* One frame (Sec. 6.1, Alg. 1; Sec. 6.2).  Pixel (i, j), row 0 at the top,
  * has a = (2i+1-W)/W, b = (H-2j-1)/H.  Orthographic: origin
@@ -266,7 +267,14 @@ ro_status ro_rebuild_residency(ro_octree *t, void *stream);
  * colour = alpha * sum(alpha_c rgb_c) / sum(alpha_c); samples composite
  * front to back (premultiplied), and a ray stops once its opacity reaches
  * term_alpha.  Empty-space skipping and the traversal start level change no
- * output. */
+ * output.
+ * RO_RENDER_ADAPTIVE_STEP (Sec. 6.1: the sampling distance may grow with the
+ * resolution level): at sample k let l_s = clamp(#{l >= 1 : t >= D_l},
+ * min lod_lo, min lod_hi), the finest desired level over the visible
+ * channels, and r its x factor (a power of two).  The sample is evaluated
+ * only when k is a multiple of r (so skipping resumes on the same grid), and
+ * its mixed opacity becomes 1 - (1 - alpha)^r with the premultiplied colour
+ * scaled by the same factor.  Where l_s = 0 the frame is unchanged. */
 typedef struct {
     uint32_t frame;     /* frame number written into slot stamps, < 0xFFFFFFFF */
     int32_t projection; /* RO_PROJ_ORTHO or RO_PROJ_PERSP */

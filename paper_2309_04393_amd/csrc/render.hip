@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
     q.min_idle = RO_MIN_IDLE;
     uint32_t st[6] = {0, 0, 0, 0, 0, 0};
     const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
-    render_rays<NV, BPV, AOV, EC>(A, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
+    render_rays<NV, BPV, AOV, EC, EC == 0>(A, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
     if (A.stats) {
         // every lane of the workgroup is here: reduce over the wave, one atomic per wave
 #pragma unroll
@@ -101,10 +101,11 @@ static hipError_t launch_one(const RenderArgs &A, const QueueLaunch &Q, hipStrea
 }
 
 // Compile-time brick edges: 32^3 and 16^3 bricks with their halo (the AOV
-// diagnostic output takes the generic kernel).
+// diagnostic output and the LOD-adaptive step take the generic kernel).
 template <int NV, int BPV>
 static hipError_t launch_nv(const RenderArgs &A, bool aov, const QueueLaunch &Q, hipStream_t s) {
     if (aov) return launch_one<NV, BPV, true, 0>(A, Q, s);
+    if (A.flags & RO_RENDER_ADAPTIVE_STEP) return launch_one<NV, BPV, false, 0>(A, Q, s);
     if (A.E == 34) return launch_one<NV, BPV, false, 34>(A, Q, s);
     if (A.E == 18) return launch_one<NV, BPV, false, 18>(A, Q, s);
     return launch_one<NV, BPV, false, 0>(A, Q, s);
@@ -185,6 +186,12 @@ ro_status build_render_args(ro_octree *tr, const ro_frame_desc *fd, float *rgba,
     for (int j = 0; j < fd->n_vis; ++j) A.ident = A.ident && fd->vis[j] == j;
     A.uni = 1;
     for (int j = 0; j < fd->n_vis; ++j) A.uni = A.uni && fd->lod_lo[j] == fd->lod_lo[0] && fd->lod_hi[j] == fd->lod_hi[0];
+    // min_c clamp(l, lo_c, hi_c) = clamp(l, min_c lo_c, min_c hi_c)
+    A.step_lo = A.step_hi = kMaxL;
+    for (int j = 0; j < fd->n_vis; ++j) {
+        A.step_lo = fd->lod_lo[j] < A.step_lo ? fd->lod_lo[j] : A.step_lo;
+        A.step_hi = fd->lod_hi[j] < A.step_hi ? fd->lod_hi[j] : A.step_hi;
+    }
     for (int j = 0; j < fd->n_vis; ++j) {
         A.vis[j] = fd->vis[j];
         A.lo[j] = fd->lod_lo[j];

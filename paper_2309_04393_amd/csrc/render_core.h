@@ -22,6 +22,7 @@ struct RenderArgs {
     uint32_t frame, flags;
     int32_t ident;  // visible slot j shows channel j for every channel, and m % 4 == 0
     int32_t uni;    // every visible channel has the same level range (lo[0], hi[0])
+    int32_t step_lo, step_hi;  // adaptive step: the finest desired level is clamped to these
     // uniform tables copied to LDS by the workgroup
     int32_t vis[kMaxC], lo[kMaxC], hi[kMaxC];
     uint32_t W0[kMaxC], W1[kMaxC];
@@ -286,7 +287,9 @@ __host__ __device__ constexpr size_t slot_bytes(int e, int bpv) {
 
 // EC: the brick edge with halo known at compile time (0: read from A).  A
 // constant edge turns the four gather offsets into instruction immediates.
-template <int NV, int BPV, bool AOV, int EC, class Source>
+// ADAPT: whether the LOD-adaptive step is compiled in (frames that ask for it
+// go to a kernel that has it).
+template <int NV, int BPV, bool AOV, int EC, bool ADAPT, class Source>
 __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, const float4 *s_tf,
                                             const ChanLds *s_ch, const uint32_t *s_runs, const LevLds *s_lv,
                                             const NodeLds *s_nd, uint32_t stats[6], LdsSlots slot) {
@@ -299,6 +302,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     const uint32_t vismask = (nvis >= 32) ? 0xFFFFFFFFu : ((1u << nvis) - 1u);
     const int s0 = A.start_level;
     const bool noskip = (A.flags & RO_RENDER_NO_SKIP) != 0;
+    const bool adaptive = ADAPT && (A.flags & RO_RENDER_ADAPTIVE_STEP) != 0;
     const NodeLds leafl = s_nd[D];
     const bool single = s_ch[0].single != 0;
     uint32_t st_samples = 0, st_reads = 0, st_miss = 0, st_visits = 0, st_nonempty = 0, st_iters = 0;
@@ -477,6 +481,18 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         }
         const int iu[3] = {(int)u[0], (int)u[1], (int)u[2]};
         while (lod + 1 < L && (unsigned long long)k >= s_lv[lod + 1].K) ++lod;
+        // LOD-adaptive step: the finest desired level over the visible
+        // channels sets the sampling distance, r = its x factor; only samples
+        // with k a multiple of r are evaluated
+        int rsh = 0;
+        if (adaptive) {
+            rsh = (int)field(s_lv[min(max(lod, A.step_lo), A.step_hi)].raw, 0);
+            const long long rm = (1ll << rsh) - 1;
+            if (k & rm) {
+                skip_to = (k | rm) + 1;
+                continue;
+            }
+        }
         const uint32_t leaf = node_at(leafl, iu[0] >> field(leafl.nsh, 0), iu[1] >> field(leafl.nsh, 1),
                                       iu[2] >> field(leafl.nsh, 2));
         if (leaf != cur_leaf || lod != cur_lod) {
@@ -788,15 +804,30 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
             asm volatile("" ::: "memory");
         }
         if (sa > 0.0f) {
-            const float as = 1.0f - prod;
-            const float sc = as / sa;
-            Cr += Tr * (double)(sr * sc);
-            Cg += Tr * (double)(sg * sc);
-            Cb += Tr * (double)(sbl * sc);
-            Tr *= 1.0 - (double)as;
+            if (rsh == 0) {
+                const float as = 1.0f - prod;
+                const float sc = as / sa;
+                Cr += Tr * (double)(sr * sc);
+                Cg += Tr * (double)(sg * sc);
+                Cb += Tr * (double)(sbl * sc);
+                Tr *= 1.0 - (double)as;
+            } else {
+                // opacity correction for a sample standing for r base steps:
+                // transparency prod^r, colour scaled with the opacity
+                double tr = (double)prod;
+                for (int q = 0; q < rsh; ++q) tr *= tr;
+                const double sc = (1.0 - tr) / (double)sa;
+                Cr += Tr * ((double)sr * sc);
+                Cg += Tr * ((double)sg * sc);
+                Cb += Tr * ((double)sbl * sc);
+                Tr *= tr;
+            }
             if (Tr <= one_minus_term) done = true;
         }
-        ++k;
+        // the next sample: with the adaptive step the next multiple of r (the
+        // level only grows along the ray, so no grid point lies in between);
+        // each lane keeps its own phase and samples on every iteration
+        k += 1ll << rsh;
     }
     stats[0] = st_samples;
     stats[1] = st_reads;

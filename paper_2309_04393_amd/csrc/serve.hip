@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
         q.min_idle = 64;
         uint32_t st[6] = {0, 0, 0, 0, 0, 0};
         const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
-        render_rays<NV, BPV, false, EC>(sA, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
+        render_rays<NV, BPV, false, EC, true>(sA, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
         if (sA.stats) {
 #pragma unroll
             for (int j = 0; j < 6; ++j) {

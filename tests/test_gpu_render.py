@@ -18,6 +18,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
+from paper_2309_04393_amd import resoct  # noqa: E402
 from paper_2309_04393_amd.pipeline import GpuScene  # noqa: E402
 
 
@@ -67,7 +68,8 @@ class Pair:
         ids, cnt, nu, tot = self.gpu.cache.read_requests(1 << 20)
         used, nused = self.gpu.cache.read_usage(f)
         fr, keep = oracle.make_frame(cam, W, H, step, chans, term_margin=term_margin,
-                                     lod_bias=kw.get("lod_bias", 1.0))
+                                     lod_bias=kw.get("lod_bias", 1.0),
+                                     adaptive=bool(kw.get("flags", 0) & resoct.RENDER_ADAPTIVE_STEP))
         o = oracle.render(self.V, self.src.levels, self.sim.res_slot, self.leaf_mm, fr, self.S, aov=aov)
         self.sim.touch(f, o["used"])
         out = dict(gpu=gpu_rgba(r["rgba"], H, W), ref=o["rgba"], o=o, ids=ids, cnt=cnt, nu=nu, tot=tot,
@@ -207,3 +209,64 @@ def test_cells_reduced_config2():
     cams = synth.orbit_path(src.dims, src.spacing, 2)
     res = p.frame(1, cams[1], 128, 128, 0.5, chans, aov=True)
     p.check_frame(res, "cells-4ch")
+
+
+def test_adaptive_step_cfg1_perspective(cfg1):
+    """LOD-adaptive step (Sec. 6.1): a perspective view whose samples fall in
+    level bands 1 and 2 (sampling distances 2 and 4 base steps), every brick
+    resident and then about half: images, requests and usage against the
+    oracle's adaptive definition, and fewer samples than the plain step."""
+    cam = synth.camera_persp((120.0, 95.0, 80.0), (32, 30, 34), (0, 0, 1), 50.0, 1.25)
+    flags = resoct.RENDER_ADAPTIVE_STEP
+    for frac, seed in ((1.0, 0), (0.5, 7)):
+        p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
+        ids = p.gpu.all_ids()
+        p.upload(0, ids[np.random.default_rng(seed).random(len(ids)) < frac])
+        p.check_masks()
+        res = p.frame(1, cam, 100, 80, 0.5, _cfg1_chans(0, 2), lod_bias=3.0, aov=True, flags=flags)
+        p.check_frame(res, f"cfg1-adaptive-{frac}")
+        amb = res["o"]["amb_pix"] == 0
+        assert np.array_equal(res["aov"][amb], res["o"]["aov"][amb])
+        plain = p.frame(2, cam, 100, 80, 0.5, _cfg1_chans(0, 2), lod_bias=3.0)
+        assert res["o"]["stats"]["samples"] < 0.8 * plain["o"]["stats"]["samples"]
+        assert res["gpu"][..., 3].max() > 0.1
+
+
+def test_adaptive_step_cells_channel_ranges():
+    """Adaptive step with per-channel level ranges (Sec. 6.2): the finest
+    desired level over the channels sets the distance (min of the ranges),
+    four u16 channels, partial residency with substitution."""
+    src = synth.CellVolume((256, 256, 64), 4, spacing=(1, 1, 4), n_levels=5, seed=2)
+    src.levels = [[src.level_array(c, l) for l in range(src.n_levels)] for c in range(4)]
+    p = Pair(src, 32, (16, 16, 4), 4, n_slots=200, max_batch=512)
+    ids = p.gpu.all_ids()
+    rng = np.random.default_rng(5)
+    rng.shuffle(ids)
+    p.upload(0, ids[:160])
+    p.check_masks()
+    ranges = [(1, 4), (2, 4), (1, 3), (3, 4)]
+    chans = [dict(c=c, lo=lo, hi=hi, W0=300 * 256, W1=8000 * 256, tf=synth.tf_hue(c / 4.0, 0.1))
+             for c, (lo, hi) in enumerate(ranges)]
+    cam = synth.camera_persp((380.0, -120.0, 420.0), (128, 128, 128), (0, 0, 1), 45.0, 1.0)
+    res = p.frame(1, cam, 128, 128, 0.5, chans, lod_bias=1.5, aov=True, flags=resoct.RENDER_ADAPTIVE_STEP)
+    p.check_frame(res, "cells-adaptive")
+    amb = res["o"]["amb_pix"] == 0
+    assert np.array_equal(res["aov"][amb], res["o"]["aov"][amb])
+
+
+def test_adaptive_step_at_finest_level_changes_nothing(cfg1):
+    """Where the finest desired level is 0 the adaptive frame is the plain
+    frame, bit for bit (images, requests, usage)."""
+    p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
+    ids = p.gpu.all_ids()
+    p.upload(0, ids[np.random.default_rng(3).random(len(ids)) < 0.6])
+    cam = synth.camera_oblique_ortho((64, 64, 64), (1, 1, 1), 2, 96, 80)
+    outs = []
+    for f, flags in ((1, 0), (2, resoct.RENDER_ADAPTIVE_STEP)):
+        r = p.gpu.render(f, cam, 96, 80, 0.5, _cfg1_chans(0, 0), flags=flags)
+        torch.cuda.synchronize()
+        ids_, cnt, nu, tot = p.gpu.cache.read_requests(1 << 20)
+        used, _ = p.gpu.cache.read_usage(f)
+        outs.append((r["rgba"].cpu().numpy().copy(), ids_.copy(), cnt.copy(), np.sort(used)))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)

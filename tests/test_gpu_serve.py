@@ -49,7 +49,8 @@ def _chans(sub, seed):
 
 def _requests(src, seed, n=6):
     """Uneven viewports (ragged tiles, a single pixel), channel subsets in
-    any order, perspective and orthographic cameras."""
+    any order, perspective and orthographic cameras; every third request
+    with the LOD-adaptive step."""
     rng = np.random.default_rng(seed)
     sizes = [(64, 48), (100, 70), (33, 17), (128, 128), (1, 1), (200, 90), (40, 160), (96, 33)]
     cams = synth.orbit_path(src.dims, src.spacing, 16, az_step_deg=23.0, az0_deg=float(seed))
@@ -63,7 +64,8 @@ def _requests(src, seed, n=6):
         else:
             cam = dict(cams[k])
             cam["tx"] = cam["ty"] * W / H
-        reqs.append(dict(W=W, H=H, cam=cam, chans=_chans(sub, seed * 31 + k), frame=2 + k))
+        reqs.append(dict(W=W, H=H, cam=cam, chans=_chans(sub, seed * 31 + k), frame=2 + k,
+                         flags=resoct.RENDER_ADAPTIVE_STEP if k % 3 == 2 else 0))
     return reqs
 
 
@@ -76,7 +78,8 @@ class Rig:
     def fd(self, k, stats=True):
         r = self.reqs[k]
         return resoct.frame_desc(r["frame"], r["cam"], r["W"], r["H"], 0.5, r["chans"], self.tf[k],
-                                 self.s.vol.n_levels, stats=self.stats[k] if stats else None)
+                                 self.s.vol.n_levels, stats=self.stats[k] if stats else None,
+                                 flags=r.get("flags", 0))
 
     def out(self, k, fill=np.nan):
         r = self.reqs[k]
@@ -171,7 +174,8 @@ def test_served_request_matches_oracle(scene):
     from tests.helpers import leaf_grid
     lg = leaf_grid(src.dims, (16, 16, 4), 5)
     leaf_mm = np.stack([src.leaf_minmax(c, (16, 16, 4), lg) for c in range(src.n_channels)])
-    fr, keep = oracle.make_frame(r["cam"], r["W"], r["H"], 0.5, r["chans"], term_margin=1e-6)
+    assert r["flags"] & resoct.RENDER_ADAPTIVE_STEP
+    fr, keep = oracle.make_frame(r["cam"], r["W"], r["H"], 0.5, r["chans"], term_margin=1e-6, adaptive=True)
     ref = oracle.render(V, src.levels, res_slot, leaf_mm, fr, len(ids))
     st = compare_images(rig.image(0, o), ref["rgba"], ref["amb_pix"])
     _report("serve-oracle", W=r["W"], H=r["H"], channels=len(r["chans"]), **st)
