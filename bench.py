@@ -158,10 +158,10 @@ def restore(scene, snap):
     scene.cache.load_state(host)
 
 
-def oracle_window(cfg, cam, W, H, x0, y0, tile, step, chans, need=2):
+def oracle_window(cfg, cam, W, H, x0, y0, tile, step, chans, need=2, first=0, adaptive=False):
     """Oracle inputs for the tile x tile pixel window at (x0, y0) of a W x H
-    frame: the volume description, level data materialised (levels below
-    `need`) over the bounding box of the window's rays, the boxes, leaf
+    frame: the volume description, level data materialised (levels first ..
+    need - 1) over the bounding box of the window's rays, the boxes, leaf
     metadata and the oracle frame of the window's sub-camera."""
     import oracle
     vol = cfg["vol"]
@@ -194,7 +194,7 @@ def oracle_window(cfg, cam, W, H, x0, y0, tile, step, chans, need=2):
     levels, boxes = [], np.zeros((vol.n_channels, vol.n_levels, 6), np.int32)
     per_level = []
     for l in range(vol.n_levels):
-        if l >= need:
+        if l >= need or l < first:
             per_level.append(None)
             continue
         a = lo // lf[l]
@@ -215,7 +215,8 @@ def oracle_window(cfg, cam, W, H, x0, y0, tile, step, chans, need=2):
         levels.append(row)
     lm = leaf_mm_all(cfg)
     fr, keep = oracle.make_frame(sub_camera(cam, W, H, x0, y0, tile), tile, tile, step,
-                                 [dict(ch, hi=vol.n_levels - 1) for ch in chans], term_margin=1e-6)
+                                 [dict(ch, hi=vol.n_levels - 1) for ch in chans], term_margin=1e-6,
+                                 adaptive=adaptive)
     return V, levels, boxes, lm, fr
 
 

@@ -20,6 +20,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import bench  # noqa: E402
+from paper_2309_04393_amd import resoct  # noqa: E402
 from paper_2309_04393_amd.pipeline import GpuScene  # noqa: E402
 from tests.test_gpu_render import _report  # noqa: E402
 
@@ -34,6 +35,17 @@ MAX_AMB = 1e-2
 
 
 def test_cfg3_window_parity():
+    """The timed frame (mid-path, every sample at level 0)."""
+    _window_parity(bench.config("cfg3")["f0"], 0, 3, 0, "cfg3-window")
+
+
+def test_cfg3_adaptive_window_parity():
+    """A zoomed-out frame of the same path (its samples want level 2) with
+    the LOD-adaptive step; level data materialised for levels 2 and 3."""
+    _window_parity(40, resoct.RENDER_ADAPTIVE_STEP, 4, 2, "cfg3-adaptive-window")
+
+
+def _window_parity(f, flags, need, first, name):
     cfg = bench.config("cfg3")
     vol = cfg["vol"]
     scene = GpuScene(vol, cfg["B"], cfg["leaf"], cfg["depth"], 60000, max_batch=4096,
@@ -46,14 +58,16 @@ def test_cfg3_window_parity():
     step = 0.5 * min(vol.spacing)
     W, H = cfg["W"], cfg["H"]
     x0, y0 = (W - TILE) // 2, (H - TILE) // 2
-    cam = cams[cfg["f0"]]
+    cam = cams[f]
     sub = bench.sub_camera(cam, W, H, x0, y0, TILE)
-    V, levels, boxes, lm, fr = bench.oracle_window(cfg, cam, W, H, x0, y0, TILE, step, chans, need=3)
+    adaptive = bool(flags & resoct.RENDER_ADAPTIVE_STEP)
+    V, levels, boxes, lm, fr = bench.oracle_window(cfg, cam, W, H, x0, y0, TILE, step, chans, need=need,
+                                                   first=first, adaptive=adaptive)
     ids_all = oracle.dense_ids(V)
     dense_of = {int(i): k for k, i in enumerate(ids_all)}
 
     # 1. empty cache: nothing drawn, every desired brick requested
-    r = scene.render(1, sub, TILE, TILE, step, chans)
+    r = scene.render(1, sub, TILE, TILE, step, chans, flags=flags)
     torch.cuda.synchronize()
     g_ids, g_cnt, nu, tot = scene.cache.read_requests(1 << 20)
     empty = np.full(len(ids_all), -1, np.int32)
@@ -61,7 +75,7 @@ def test_cfg3_window_parity():
     assert not np.isnan(o["rgba"]).any()
     n_req = compare_requests(g_ids, g_cnt, o["counts"], o["amb_counts"], ids_all)
     compare_images(gpu_rgba(r["rgba"], TILE, TILE), o["rgba"], o["amb_pix"], max_amb_frac=MAX_AMB)
-    _report("cfg3-window-empty", requests=n_req, missing=tot, samples=o["stats"]["samples"])
+    _report(f"{name}-empty", requests=n_req, missing=tot, samples=o["stats"]["samples"])
 
     # 2. three quarters of the requested bricks resident; for half of the
     # others the level above is resident instead (substitution)
@@ -83,7 +97,7 @@ def test_cfg3_window_parity():
     res = np.full(len(ids_all), -1, np.int32)
     for k, i in enumerate(up):
         res[dense_of[int(i)]] = k
-    r = scene.render(3, sub, TILE, TILE, step, chans)
+    r = scene.render(3, sub, TILE, TILE, step, chans, flags=flags)
     torch.cuda.synchronize()
     g_ids, g_cnt, nu, tot = scene.cache.read_requests(1 << 20)
     used_slots, n_used = scene.cache.read_usage(3)
@@ -100,4 +114,4 @@ def test_cfg3_window_parity():
     o_read = {int(up[s]) for s in np.nonzero(o["used"])[0]}
     o_amb = {int(up[s]) for s in np.nonzero(o["amb_used"])[0]}
     assert o_read <= g_read <= o_read | o_amb
-    _report("cfg3-window-partial", uploaded=len(up), requests=n_req, missing=tot, read=len(o_read), **st)
+    _report(f"{name}-partial", uploaded=len(up), requests=n_req, missing=tot, read=len(o_read), **st)
