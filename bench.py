@@ -355,13 +355,19 @@ def adaptive_bench(scene, fl, frames, reps=3):
     from paper_2309_04393_amd import resoct
     out = {}
     for f in frames:
-        for _ in range(4):
+        for it in range(3):
             fl.render(f)
             ids, cnt, nu, tot = scene.cache.read_requests(1 << 22)
+            log(f"adaptive step, frame {f}: warm-up {it}: {nu} bricks requested")
             if nu == 0:
                 break
+            order = np.lexsort((ids, -cnt.astype(np.int64)))
+            ids = ids[order][: scene.cache.n_slots]
+            t = time.perf_counter()
             scene.upload(f, ids)
             scene.tree.update_residency()
+            torch.cuda.synchronize()
+            log(f"  uploaded {len(ids)} bricks in {time.perf_counter() - t:.1f} s")
         row = {}
         for name, flags in (("plain", 0), ("adaptive", resoct.RENDER_ADAPTIVE_STEP)):
             ms = []
@@ -553,6 +559,9 @@ def main():
     ap.add_argument("--no-streaming", action="store_true", help="skip the timing of the streaming steps")
     ap.add_argument("--no-adaptive", action="store_true",
                     help="skip the LOD-adaptive step measurement on zoomed-out frames")
+    ap.add_argument("--adaptive-frames", default="0,20",
+                    help="fly-through frames of the adaptive-step measurement (each is made resident first; "
+                         "the coarse bricks of zoomed-out frames take the host generator a while)")
     ap.add_argument("--prefetch-only", action="store_true",
                     help="only the learned-prefetcher evaluation (10 training, 5 held-out paths)")
     ap.add_argument("--pf-lr", type=float, default=3e-3)
@@ -688,7 +697,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 1 << 30
+    log(f"timed frames: {out['render_ms']:.2f} ms per frame")
     if not args.no_cpu_baseline:
+        log("oracle window (CPU baseline and parity)")
         # the oracle's window of the last timed frame, which read every sample
         # from its desired level (no missing samples), against the GPU image
         fl_last = f0 + K - 1
@@ -707,10 +718,12 @@ def main():
             out["cpu_baseline"] = {"error": repr(e)}
     # after the parity window, which reads the last timed frame's image
     if not args.no_streaming:
+        log("streaming steps")
         out["streaming"] = streaming_bench(scene, fl, cams, f_req=max(f0 - 60, 0), f_up=f0 + K, U=cfg["U"],
                                            mm0=mm[0])
     if not args.no_adaptive:
-        out["adaptive_step"] = adaptive_bench(scene, fl, (0, 40, 80))
+        log("LOD-adaptive step on zoomed-out frames")
+        out["adaptive_step"] = adaptive_bench(scene, fl, tuple(int(x) for x in args.adaptive_frames.split(",")))
     if args.serve > 0 or not args.no_prefetch:
         del fl, store, scene
         torch.cuda.empty_cache()
