@@ -452,24 +452,42 @@ def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True, max_batch=64):
                          "speedup": (sb / wb) / (ss / ws), "same_samples": sb == ss}}
     cap = len(sub) / wb
 
-    def at_rate(lam, seed):
+    # load shedding: batches of at most 1024 work items (about 3 full-HD
+    # requests' worth of 8x8 blocks, ~0.1 s of device time), requests queued
+    # longer than 0.1 s dropped
+    shed_loop = ServingLoop(scene, out_budget=4 << 30, max_requests=max_batch, max_tiles=1024, graph=graph)
+    shed_loop.run(sub[:4])  # graph capture
+    reset_trace(sub)
+
+    def at_rate(lam, seed, max_wait=None):
+        lp = loop if max_wait is None else shed_loop
         trace = make_trace(scene, lam, seconds, arrival_seed=seed)
-        loop.stats.zero_()
-        nb0 = loop.n_batches
-        wall = loop.run(trace, deadline=seconds + 5.0)
-        st = loop.stats.cpu().numpy()
+        lp.stats.zero_()
+        nb0 = lp.n_batches
+        wall = lp.run(trace, deadline=seconds + 5.0, max_wait=max_wait)
+        st = lp.stats.cpu().numpy()
         lat = latency_summary(trace)
-        sizes = loop.batch_sizes[nb0:]
+        sizes = lp.batch_sizes[nb0:]
         done = sum(1 for r in trace if np.isfinite(r.done))
-        return {"rate_req_per_s": lam, "seconds": seconds, "requests": len(trace), "completed": done,
-                "latency_ms": {k: v for k, v in lat.items() if k not in ("n", "completed")},
-                "wall_s": wall, "served_req_per_s": done / wall, "samples_per_s": float(st[0]) / wall,
-                "batches": len(sizes), "mean_batch": float(np.mean(sizes)) if sizes else 0.0}
+        shed = sum(1 for r in trace if r.shed)
+        res = {"rate_req_per_s": lam, "seconds": seconds, "requests": len(trace), "completed": done,
+               "latency_ms": {k: v for k, v in lat.items() if k not in ("n", "completed")},
+               "wall_s": wall, "served_req_per_s": done / wall, "samples_per_s": float(st[0]) / wall,
+               "batches": len(sizes), "mean_batch": float(np.mean(sizes)) if sizes else 0.0}
+        if max_wait is not None:
+            res["max_queue_wait_s"] = max_wait
+            res["max_batch_work_items"] = lp.max_tiles
+            res["shed"] = shed
+        log(f"serving at {lam:.1f} requests/s (max wait {max_wait}): {done} of {len(trace)} done, {shed} shed")
+        return res
 
     out["stated_load"] = at_rate(rate, 3000)
+    # the same arrivals with load shedding, so the served requests keep a
+    # bounded latency
+    out["stated_load_shedding"] = at_rate(rate, 3000, max_wait=0.1)
     out["load_70pct_capacity"] = at_rate(0.7 * cap, 3002)
     log(f"serving: {json.dumps(out)}")
-    del loop, scene
+    del loop, shed_loop, scene
     torch.cuda.empty_cache()
     return out
 

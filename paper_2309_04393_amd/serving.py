@@ -86,6 +86,7 @@ class Request:
     frame: int = 1
     admitted: float = math.nan
     done: float = math.nan
+    shed: bool = False
     mem: tuple = None
     fd: object = field(default=None, repr=False)
 
@@ -152,13 +153,16 @@ class ServingLoop:
         self.batch_sizes.append(len(batch))
         return Batch(t, batch, now)
 
-    def run(self, trace, on_done=None, idle_sleep=20e-6, deadline=None):
+    def run(self, trace, on_done=None, idle_sleep=20e-6, deadline=None, max_wait=None):
         """Serve `trace` (requests sorted by arrival, times in seconds from
         the start) in real time; returns the wall time of the run.
         on_done(request, image) is called for each finished request before
         its image memory is released.  After `deadline` seconds nothing more
         is admitted: batches in flight finish, requests still queued or not
-        yet arrived stay unfinished (done = nan)."""
+        yet arrived stay unfinished (done = nan).  With max_wait (seconds), a
+        queued request that has waited longer is shed (r.shed = True, never
+        rendered): load shedding keeps the latency of the served requests
+        bounded when arrivals exceed the capacity."""
         # the server's streams do not wait for work queued on torch's streams
         torch.cuda.synchronize()
         clock = time.perf_counter
@@ -191,6 +195,15 @@ class ServingLoop:
                 if all(r.mem is None for r in b.reqs) and self.server.poll(b.ticket):
                     inflight.remove(b)
                     progressed = True
+            if max_wait is not None and queue and now - queue[0].arrival > max_wait:
+                keep = []
+                for r in queue:
+                    if now - r.arrival > max_wait:
+                        r.shed = True
+                    else:
+                        keep.append(r)
+                queue[:] = keep
+                progressed = True
             if len(inflight) < 2 and queue:
                 batch = self._admit(queue, now)
                 if batch:
@@ -203,11 +216,11 @@ class ServingLoop:
 
 
 def latency_summary(trace, t_from=0.0):
-    """Latency percentiles over the requests arriving from t_from on; an
-    unfinished request counts as infinitely late (p50_ms / p99_ms are None
-    when that percentile is unbounded).  The *_completed_ms figures are over
-    the finished requests only."""
-    lat = np.array([r.done - r.arrival for r in trace if r.arrival >= t_from])
+    """Latency percentiles over the requests arriving from t_from on that
+    were not shed; an unfinished request counts as infinitely late (p50_ms /
+    p99_ms are None when that percentile is unbounded).  The *_completed_ms
+    figures are over the finished requests only."""
+    lat = np.array([r.done - r.arrival for r in trace if r.arrival >= t_from and not r.shed])
     if not len(lat):
         return dict(n=0)
     fin = np.isfinite(lat)
@@ -284,5 +297,6 @@ def make_trace(scene, rate: float, duration: float, n_clients: int = 64, client_
 def reset_trace(trace):
     for r in trace:
         r.admitted = r.done = math.nan
+        r.shed = False
         r.mem = None
         r.fd = None

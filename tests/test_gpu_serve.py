@@ -248,3 +248,22 @@ def test_serving_loop_real_time(scene):
         n_exact += _same(img, ref, f"loop-{r.rid}")
     _report("serve-loop", requests=len(trace), batches=loop.n_batches, mean_batch=np.mean(loop.batch_sizes),
             bit_exact=f"{n_exact}/{len(trace)}", peak_mb=loop.arena.peak / 2**20, **lat)
+
+
+def test_load_shedding_bounds_queue_wait(scene):
+    """Arrivals above capacity with a queue-wait limit: every request is
+    either served or shed, none waits in the queue longer than the limit
+    (plus one loop pass), and the served ones finish."""
+    trace = make_trace(scene, rate=600.0, duration=0.5, n_clients=16)
+    loop = ServingLoop(scene, out_budget=4 * 16 * 1920 * 1080, max_requests=16, max_tiles=1 << 15, graph=True)
+    max_wait = 0.05
+    loop.run(trace, max_wait=max_wait)
+    served = [r for r in trace if not r.shed]
+    shed = [r for r in trace if r.shed]
+    assert shed and served
+    assert all(np.isfinite(r.done) for r in served)
+    assert all(not np.isfinite(r.done) and not np.isfinite(r.admitted) for r in shed)
+    assert max(r.admitted - r.arrival for r in served) <= max_wait + 0.02
+    lat = latency_summary(trace)
+    assert lat["n"] == len(served) and np.isfinite(lat["p99_ms"])
+    _report("serve-shedding", requests=len(trace), served=len(served), shed=len(shed), **lat)
