@@ -260,6 +260,7 @@ def test_adaptive_step_at_finest_level_changes_nothing(cfg1):
     p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
     ids = p.gpu.all_ids()
     p.upload(0, ids[np.random.default_rng(3).random(len(ids)) < 0.6])
+    p.check_masks()
     cam = synth.camera_oblique_ortho((64, 64, 64), (1, 1, 1), 2, 96, 80)
     outs = []
     for f, flags in ((1, 0), (2, resoct.RENDER_ADAPTIVE_STEP)):
@@ -270,3 +271,19 @@ def test_adaptive_step_at_finest_level_changes_nothing(cfg1):
         outs.append((r["rgba"].cpu().numpy().copy(), ids_.copy(), cnt.copy(), np.sort(used)))
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (7, 3), (33, 65)])
+def test_tiny_and_ragged_viewports(cfg1, W, H):
+    """Viewports smaller than one 8x8 block and not multiples of the 32x32
+    tile: the blocks' pixels outside the image are never written and the
+    image, requests and usage match the oracle."""
+    p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
+    ids = p.gpu.all_ids()
+    p.upload(0, ids[np.random.default_rng(W * 100 + H).random(len(ids)) < 0.6])
+    p.check_masks()  # residency update (the renderer reads residency from the octree masks)
+    cam = synth.camera_persp((120.0, 95.0, 80.0), (32, 30, 34), (0, 0, 1), 30.0, W / H)
+    sentinel = torch.full((W * H * 4 + 64,), -7.0, dtype=torch.float32, device="cuda")
+    res = p.frame(1, cam, W, H, 0.5, _cfg1_chans(0, 2), lod_bias=0.6, out=sentinel)
+    p.check_frame(res, f"ragged-{W}x{H}")
+    assert (sentinel[W * H * 4:].cpu().numpy() == -7.0).all(), "wrote past the image"
