@@ -142,7 +142,12 @@ void ro_cache_destroy(ro_cache *c);
  * frame).  An ID resident at the start of the batch, or repeated earlier in
  * it, gets flag 2 and its slot's stamp is set to `frame`; uploads that find
  * no eligible slot get flag 0; inserted ones flag 1 (inserted_host[n]).
- * Evicted and inserted bricks are recorded for ro_update_residency.
+ * Evicted and inserted bricks are recorded for ro_update_residency: the
+ * page tables change at once, but the renderer picks a channel's level from
+ * the octree's residency masks, so frames see the new bricks (and stop
+ * substituting evicted ones) after ro_update_residency.  Until then a level
+ * whose mask bit is stale and whose page-table entry is empty contributes
+ * nothing at that sample (never an out-of-range read).
  * Synchronises on `stream` before returning (flags are host memory).
  * n <= max_batch; frame < 0xFFFFFFFF. */
 ro_status ro_stream_bricks(ro_cache *c, uint32_t frame, uint32_t n, const uint32_t *ids_host,
