@@ -168,3 +168,31 @@ def test_run_is_deterministic(cells):
                      p.gpu.tree.masks(), p.gpu.cache.page_table_host()))
     for u, v in zip(*outs):
         assert np.array_equal(u, v)
+
+
+def test_render_between_upload_and_residency_update(cells):
+    """Uploads that evict bricks change the page tables at once while the
+    octree masks wait for the residency update: a frame rendered in between
+    reads no evicted slot (the stale levels contribute nothing, stamps only
+    on live slots), and after the update the frame matches the oracle."""
+    p = Pair(cells, 32, (16, 16, 4), 5, n_slots=120, max_batch=128)
+    ids = p.gpu.all_ids()
+    rng = np.random.default_rng(12)
+    rng.shuffle(ids)
+    p.upload(0, ids[:110])
+    p.check_masks()
+    cams = synth.orbit_path(cells.dims, cells.spacing, 4, az_step_deg=15.0)
+    chans = _chans(4)
+    p.upload(1, ids[110:220])  # evicts most of the first batch; masks not updated
+    r = p.gpu.render(2, cams[1], 64, 64, 0.5, chans)
+    torch.cuda.synchronize()
+    img = gpu_rgba(r["rgba"], 64, 64)
+    assert np.isfinite(img).all() and img.min() >= 0.0 and img[..., 3].max() <= 1.0
+    used, n = p.gpu.cache.read_usage(2)
+    pt = p.gpu.cache.page_table_host()
+    live = set(pt[pt != 0xFFFFFFFF].tolist())
+    assert set(used.tolist()) <= live
+    p.gpu.cache.read_requests(1 << 20)  # clear the in-between frame's counters
+    p.check_masks()  # the residency update
+    res = p.frame(3, cams[1], 64, 64, 0.5, chans)
+    p.check_frame(res, "after-update")
