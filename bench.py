@@ -191,6 +191,28 @@ def oracle_window(cfg, cam, W, H, x0, y0, tile, step, chans, need=2, first=0, ad
     lo = np.clip(np.floor(lo) - 2, 0, dims - 1).astype(int)
     hi = np.clip(np.ceil(hi) + 2, 1, dims).astype(int)
     ldims, lf, _ = oracle.level_info(V)
+    if need is None:
+        # levels the window's samples desire (every brick resident): from the
+        # distance range of a grid of its rays through the volume
+        assert cam["proj"] == "persp"
+        ts = []
+        for i in np.linspace(x0, x0 + tile - 1, 17):
+            for j in np.linspace(y0, y0 + tile - 1, 17):
+                a = (2 * i + 1 - W) / W
+                b = (H - 2 * j - 1) / H
+                d = np.array(cam["F"]) + a * cam["tx"] * np.array(cam["R"]) + b * cam["ty"] * np.array(cam["U"])
+                d = d / np.linalg.norm(d) / np.array(vol.spacing)
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    t0 = np.where(d != 0, (0 - eye) / d, -np.inf)
+                    t1 = np.where(d != 0, (dims - eye) / d, np.inf)
+                ta, tb = np.max(np.minimum(t0, t1)), np.min(np.maximum(t0, t1))
+                if ta <= tb:
+                    ts += [max(ta, 0.0), tb]
+        pix = 2.0 * cam["ty"] / H
+        D = [float(lf[l][0]) * vol.spacing[0] / pix for l in range(1, vol.n_levels)]
+        lev = lambda t: sum(1 for x in D if t >= x)
+        first = lev(min(ts) * (1 - 1e-3)) if ts else 0
+        need = lev(max(ts) * (1 + 1e-3)) + 1 if ts else 1
     levels, boxes = [], np.zeros((vol.n_channels, vol.n_levels, 6), np.int32)
     per_level = []
     for l in range(vol.n_levels):
@@ -227,7 +249,7 @@ def cpu_baseline(cfg, cams, chans, f, step, tile):
     import oracle
     W, H = cfg["W"], cfg["H"]
     x0, y0 = (W - tile) // 2, (H - tile) // 2
-    V, levels, boxes, lm, fr = oracle_window(cfg, cams[f], W, H, x0, y0, tile, step, chans)
+    V, levels, boxes, lm, fr = oracle_window(cfg, cams[f], W, H, x0, y0, tile, step, chans, need=None)
     res = np.arange(oracle.brick_count(V), dtype=np.int32)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t = time.perf_counter()
@@ -238,7 +260,7 @@ def cpu_baseline(cfg, cams, chans, f, step, tile):
     # one host thread on a quarter-edge window at the same centre
     t1 = max(tile // 4, 8)
     x1, y1 = (W - t1) // 2, (H - t1) // 2
-    V1, lv1, bx1, lm1, fr1 = oracle_window(cfg, cams[f], W, H, x1, y1, t1, step, chans)
+    V1, lv1, bx1, lm1, fr1 = oracle_window(cfg, cams[f], W, H, x1, y1, t1, step, chans, need=None)
     t = time.perf_counter()
     r1 = oracle.render(V1, lv1, res, lm1, fr1, 1, n_threads=1, boxes=bx1)
     dt1 = time.perf_counter() - t
