@@ -613,7 +613,7 @@ def main():
                          "known size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
