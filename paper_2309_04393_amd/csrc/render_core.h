@@ -315,6 +315,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     float *out = nullptr;
     bool done = true;
     long long k = 0, kend = -1, skip_to = 0;  // the lane is inside an empty node while k < skip_to
+    int rpace = 0;  // adaptive step: log2 of the lane's last sampling distance (its pace while skipping)
     uint32_t cur_leaf = kInvalid;
     int cur_lod = -1, lod = 0;
     uint32_t emask = 0, missmask = 0;
@@ -383,6 +384,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         cur_leaf = kInvalid;
         cur_lod = -1;
         lod = 0;
+        rpace = 0;
         while (lod + 1 < L && (unsigned long long)k >= s_lv[lod + 1].K) ++lod;
         emask = missmask = 0;
         lvpack = 0;
@@ -464,7 +466,10 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         ++st_iters;  // a stepping iteration of the wave (lane busy or idle)
         if (!active) continue;
         if (k < skip_to) {
-            ++k;
+            // a skipping lane keeps the pace of the sampling lanes (one base
+            // step, or the band's distance with the adaptive step) so the
+            // wave's lanes stay at neighbouring depths
+            k = ADAPT ? min(skip_to, k + (1ll << rpace)) : k + 1;
             continue;
         }
         const double t = (double)k * A.step;
@@ -487,6 +492,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         int rsh = 0;
         if (adaptive) {
             rsh = (int)field(s_lv[min(max(lod, A.step_lo), A.step_hi)].raw, 0);
+            rpace = rsh;
             const long long rm = (1ll << rsh) - 1;
             if (k & rm) {
                 skip_to = (k | rm) + 1;
