@@ -1,0 +1,28 @@
+"""CPU checks of the measurement script's command line: more than one GPU is
+refused with a JSON message before any GPU work, and the argument parser
+accepts the documented options."""
+from __future__ import annotations
+
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", "--steps", "1"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_help_lists_the_measurement_options():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
+                       timeout=120, cwd=ROOT)
+    assert r.returncode == 0
+    for opt in ("--gpus", "--steps", "--warmup", "--serve", "--no-prefetch", "--no-streaming", "--no-adaptive",
+                "--copy-calibration", "--tile"):
+        assert opt in r.stdout
