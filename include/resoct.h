@@ -297,7 +297,7 @@ typedef struct {
     const float *tf_dev;  /* device [n_vis][256][4] RGBA, alpha >= 0 */
     float term_alpha;     /* in (0, 1] */
     int32_t start_level;  /* traversal start level (Sec. 6, implementation), -1: the octree's */
-    uint32_t flags;       /* RO_RENDER_* */
+    uint32_t flags;       /* RO_RENDER_*; other bits are rejected (RO_E_ARG) */
     uint32_t *aov_dev;    /* RO_RENDER_AOV: device [H][W][k] uint32, zeroed by the caller */
     unsigned long long *stats_dev; /* optional device [8], accumulated (not cleared): [0] ray
                                       samples evaluated, [1] channel samples read from bricks,

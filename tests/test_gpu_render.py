@@ -287,3 +287,18 @@ def test_tiny_and_ragged_viewports(cfg1, W, H):
     res = p.frame(1, cam, W, H, 0.5, _cfg1_chans(0, 2), lod_bias=0.6, out=sentinel)
     p.check_frame(res, f"ragged-{W}x{H}")
     assert (sentinel[W * H * 4:].cpu().numpy() == -7.0).all(), "wrote past the image"
+
+
+def test_render_argument_errors(cfg1):
+    """Frame descriptors the ABI rejects before any launch (RO_E_ARG):
+    unknown flag bits, an empty viewport, an inverted level range."""
+    p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
+    cam = synth.camera_oblique_ortho((64, 64, 64), (1, 1, 1), 1, 16, 16)
+    for kw, chans, W in ((dict(flags=8), _cfg1_chans(0, 2), 16), ({}, _cfg1_chans(0, 2), 0),
+                         ({}, _cfg1_chans(2, 1), 16)):
+        with pytest.raises(resoct.ResoctError) as e:
+            p.gpu.render(1, cam, W, 16, 0.5, chans, **kw)
+        assert e.value.code == -1
+    r = p.gpu.render(1, cam, 16, 16, 0.5, _cfg1_chans(0, 2))  # still usable
+    torch.cuda.synchronize()
+    assert np.isfinite(gpu_rgba(r["rgba"], 16, 16)).all()
