@@ -168,9 +168,10 @@ class Volume:
         self.bytes_per_voxel = bytes_per_voxel
         self.dims = tuple(int(x) for x in dims)
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.ro_volume_destroy):
+        # bound when the class is created: module globals may be gone at interpreter exit
         if getattr(self, "h", None):
-            _lib.ro_volume_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def levels(self):
@@ -219,9 +220,10 @@ class Cache:
         self.h = h
         self.n_bricks = vol.brick_count()
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.ro_cache_destroy):
+        # bound when the class is created: module globals may be gone at interpreter exit
         if getattr(self, "h", None):
-            _lib.ro_cache_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def staging(self, n: int, device="cuda") -> torch.Tensor:
@@ -292,9 +294,10 @@ class Octree:
         self.h = h
         self.depth = depth
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.ro_octree_destroy):
+        # bound when the class is created: module globals may be gone at interpreter exit
         if getattr(self, "h", None):
-            _lib.ro_octree_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def set_leaf_metadata(self, channel: int, leaf_mm: torch.Tensor, stream=None):
@@ -387,9 +390,10 @@ class Mlp:
         _check(_lib.ro_mlp_create(_dev_ptr(self.params), _dev_ptr(self.work), ctypes.byref(h)), "ro_mlp_create")
         self.h = h
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.ro_mlp_destroy):
+        # bound when the class is created: module globals may be gone at interpreter exit
         if getattr(self, "h", None):
-            _lib.ro_mlp_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def set_weights(self, p: dict, stream=None):
@@ -447,9 +451,10 @@ class PrefetchRows:
         self.h = h
         self.tree = tree
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.ro_pf_destroy):
+        # bound when the class is created: module globals may be gone at interpreter exit
         if getattr(self, "h", None):
-            _lib.ro_pf_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def record(self, frame: int, stream=None):
@@ -507,9 +512,10 @@ class Server:
         self.tree = tree
         self.max_requests, self.max_tiles = max_requests, max_tiles
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.ro_serve_destroy):
+        # bound when the class is created: module globals may be gone at interpreter exit
         if getattr(self, "h", None):
-            _lib.ro_serve_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def prepare(self, fds, outs, full_channels=False):
