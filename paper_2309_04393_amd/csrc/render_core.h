@@ -161,24 +161,9 @@ struct LdsSlots {
     __device__ __forceinline__ uint32_t &operator[](int j) { return p[(uint32_t)j * stride]; }
 };
 
-// Pixel sources of the stepping loop.  A source hands a lane its first
-// pixel and, if it refills, further pixels when lanes of the wave are idle.
+// Pixel source of the stepping loop (first pixel of each lane, further
+// pixels when lanes of the wave are idle).
 //
-// OnePixel: the lane's one pixel (the serving kernel's tile lanes).
-struct OnePixel {
-    static constexpr bool kRefill = false;
-    int px, py;
-    bool valid;
-    __device__ __forceinline__ bool first(int &x, int &y, bool &v) {
-        x = px;
-        y = py;
-        v = valid;
-        return true;
-    }
-    __device__ __forceinline__ bool refill(uint64_t, int &, int &, bool &) { return false; }
-    __device__ __forceinline__ bool more() const { return false; }
-};
-
 // BlockQueue: waves take 8 x 8-pixel blocks from device counters (blocks of
 // a 32 x 32 tile are consecutive, tiles in raster order).  With n_queues = 1
 // one counter hands out the blocks in order.  With n_queues > 1 the blocks
