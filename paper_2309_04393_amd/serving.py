@@ -225,7 +225,11 @@ def latency_summary(trace, t_from=0.0):
         return dict(n=0)
     fin = np.isfinite(lat)
     lat = np.where(fin, lat, np.inf)
-    pct = lambda q: float(np.percentile(lat, q) * 1e3) if np.isfinite(np.percentile(lat, q)) else None
+
+    def pct(q):
+        with np.errstate(invalid="ignore"):  # interpolation next to infinite entries
+            v = np.percentile(lat, q)
+        return float(v * 1e3) if np.isfinite(v) else None
     done = lat[fin]
     return dict(n=int(len(lat)), completed=int(fin.sum()), p50_ms=pct(50), p99_ms=pct(99),
                 mean_ms=float(done.mean() * 1e3) if fin.any() else None,
