@@ -364,6 +364,29 @@ def streaming_bench(scene, fl, cams, f_req, f_up, U, mm0):
     _, ms = timed(lambda: scene.tree.set_leaf_metadata(0, t))
     out["a11_metadata_one_channel"] = entry(ms, 4 * scene.tree.n_leaves + 4 * scene.tree.n_nodes,
                                             note="leaf (min, max) read + one metadata word written per node")
+    # metadata computed from the voxels of the uploaded channel-0 bricks;
+    # then the server's metadata of channel 0 is restored
+    L = scene.vol.n_levels
+    c0 = up[(up >> 24) // L == 0]
+    if len(c0):
+        n_up = scene.tree.n_nodes - scene.tree.n_leaves
+        lg = scene.tree.leaf_grid
+        leaves = 0
+        for i in c0:  # leaves of the padded grid inside each brick
+            _, l, b = scene.vol.decode(int(i))
+            n = 1
+            for a in range(3):
+                per = scene.B * int(scene.lf[l][a]) // scene.leaf[a]
+                n *= max(min((b[a] + 1) * per, lg[a]) - b[a] * per, 0)
+            leaves += n
+        _, ms = timed(lambda: scene.tree.leaf_metadata_from_bricks(c0))
+        out["f3_metadata_from_bricks"] = entry(
+            ms, len(c0) * c.slot_stride + 4 * leaves + 36 * n_up, bricks=len(c0), leaves=leaves,
+            note="each brick's slot read once + one metadata word per leaf inside the bricks + the inner "
+                 "nodes of the channel reduced again (8 children read, 1 written); includes the host "
+                 "work-list copy")
+        scene.tree.set_leaf_metadata(0, t)
+        torch.cuda.synchronize()
     return out
 
 

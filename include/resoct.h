@@ -231,6 +231,26 @@ void ro_octree_destroy(ro_octree *t);
 ro_status ro_octree_set_leaf_metadata(ro_octree *t, uint32_t channel,
                                       const uint16_t *leaf_minmax_dev, void *stream);
 
+/* Leaf metadata computed from resident brick data (Sec. 5.3: a client whose
+ * server has no metadata derives it from the voxels it fetched; the
+ * application picks the resolution level).  ids_host[n]: brick IDs, each
+ * resident (else RO_E_STATE) and in range (else RO_E_ARG); on either error
+ * nothing changes.  Every leaf of the padded grid inside such a brick's
+ * extent gets, for the brick's channel, [min, max] over the voxels of the
+ * brick's level that overlap the leaf box dilated by one voxel of that level
+ * and clamped to the level's grid ([0, 0] if nothing is left): at level 0
+ * exactly the conservative metadata ro_octree_set_leaf_metadata asks for; at
+ * coarser levels an estimate from fewer voxels, which may miss extremes.
+ * Where bricks of several levels cover one leaf, the finest level's values
+ * stay.  Leaves outside the given bricks keep their metadata: to keep them
+ * from being skipped before their data arrive, give them [0, max raw value]
+ * first (unknown = never empty).  Inner nodes of the touched channels are
+ * then reduced again.  Reads the slots: call it after the ro_stream_bricks
+ * that uploaded them, on the same stream or after it has completed.  Returns
+ * after the work is queued (it waits for its own copies of the work list). */
+ro_status ro_octree_leaf_metadata_from_bricks(ro_octree *t, uint32_t n, const uint32_t *ids_host,
+                                              void *stream);
+
 /* Residency update for the bricks inserted or evicted since the last call
  * (Sec. 5.3): each leaf overlapping such a brick gets bit l of its channel's
  * mask set iff the level-l brick containing it is resident; then every

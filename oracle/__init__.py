@@ -158,6 +158,47 @@ def meta_all(V: Volume, leaf_mm: np.ndarray) -> np.ndarray:
     return out
 
 
+def leaf_meta_from_bricks(V: Volume, levels, leaf_mm: np.ndarray, brick_ids) -> np.ndarray:
+    """Sec. 5.3, metadata computed on the client from fetched brick voxels
+    (plain numpy over the definition).  levels[c][l]: level arrays [z][y][x];
+    leaf_mm: [C][n_leaves][2] before the call; brick_ids: IDs of the bricks
+    whose data are used.  Returns the new leaf metadata: each leaf of the
+    padded leaf grid inside a brick's extent gets, for the brick's channel,
+    [min, max] of the voxels of the brick's level that overlap the leaf box
+    grown by one voxel of that level, clamped to the level's grid ([0, 0] if
+    nothing is left).  Bricks are applied coarsest level first, so where
+    several cover a leaf the finest level's values stay."""
+    d, f, nb = level_info(V)
+    _, _, n = node_count(V)
+    ng = [int(x) for x in n[V.depth]]
+    lf = [int(x) for x in V.leaf]
+    out = np.array(leaf_mm, dtype=np.uint16, copy=True)
+    bricks = sorted({brick_id_decode(V.n_levels, int(i)) for i in brick_ids}, key=lambda t: -t[1])
+    for c, l, bx, by, bz in bricks:
+        arr = levels[c][l]
+        b = (bx, by, bz)
+        rng = []
+        for a in range(3):
+            e0 = b[a] * V.B * int(f[l][a])  # the brick's extent in L0 voxels
+            e1 = e0 + V.B * int(f[l][a])
+            rng.append(range(min(e0 // lf[a], ng[a]), min(e1 // lf[a], ng[a])))
+        for lz in rng[2]:
+            for ly in rng[1]:
+                for lx in rng[0]:
+                    box = []
+                    for a, li in enumerate((lx, ly, lz)):
+                        x0, x1, fa = li * lf[a], (li + 1) * lf[a], int(f[l][a])
+                        box.append((max(x0 // fa - 1, 0), min((x1 - 1) // fa + 1, int(d[l][a]) - 1)))
+                    k = (lz * ng[1] + ly) * ng[0] + lx
+                    if any(lo > hi for lo, hi in box):
+                        out[c, k] = (0, 0)
+                        continue
+                    (x0, x1), (y0, y1), (z0, z1) = box
+                    sub = arr[z0:z1 + 1, y0:y1 + 1, x0:x1 + 1]
+                    out[c, k] = (sub.min(), sub.max())
+    return out
+
+
 def masks(V: Volume, res_slot: np.ndarray) -> np.ndarray:
     tot, _, _ = node_count(V)
     out = np.zeros((tot, V.n_channels), np.uint16)

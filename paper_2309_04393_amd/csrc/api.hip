@@ -494,6 +494,27 @@ extern "C" ro_status ro_octree_set_leaf_metadata(ro_octree *t, uint32_t channel,
     return octree_set_meta(t, channel, leaf_mm, (hipStream_t)stream);
 }
 
+extern "C" ro_status ro_octree_leaf_metadata_from_bricks(ro_octree *t, uint32_t n, const uint32_t *ids,
+                                                        void *stream) {
+    RO_CHECK(t && (ids || n == 0), RO_E_ARG, "null argument");
+    const VolGeo &g = t->cache->vol->g;
+    // (coarsest level first, dense index) so that finer levels are written last
+    std::vector<std::pair<int, uint32_t>> order;
+    order.reserve(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t c, l, b[3];
+        RO_CHECK(decode_id(g, ids[i], &c, &l, b), RO_E_ARG, "brick ID 0x%08x out of range", ids[i]);
+        const uint32_t dn = dense_index(g, (int)c, (int)l, (int)b[0], (int)b[1], (int)b[2]);
+        RO_CHECK(t->cache->pt_host[dn] != kInvalid, RO_E_STATE, "brick 0x%08x is not resident", ids[i]);
+        order.emplace_back(g.L - 1 - (int)l, dn);
+    }
+    std::sort(order.begin(), order.end());
+    order.erase(std::unique(order.begin(), order.end()), order.end());
+    std::vector<uint32_t> dense(order.size());
+    for (size_t i = 0; i < order.size(); ++i) dense[i] = order[i].second;
+    return octree_meta_from_bricks(t, dense, (hipStream_t)stream);
+}
+
 extern "C" ro_status ro_update_residency(ro_octree *t, void *stream) {
     RO_CHECK(t, RO_E_ARG, "null octree");
     std::vector<uint32_t> d;

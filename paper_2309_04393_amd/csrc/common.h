@@ -149,6 +149,7 @@ ro_status read_usage_device(ro_cache *c, uint32_t frame, uint32_t cap, uint32_t 
 ro_status octree_set_meta(ro_octree *t, uint32_t channel, const uint16_t *leaf_mm, hipStream_t s);
 ro_status octree_update(ro_octree *t, const std::vector<uint32_t> &dirty, hipStream_t s);
 ro_status octree_rebuild(ro_octree *t, hipStream_t s);
+ro_status octree_meta_from_bricks(ro_octree *t, const std::vector<uint32_t> &dense, hipStream_t s);
 
 ro_status render_device(ro_octree *t, const ro_frame_desc *fd, float *rgba, hipStream_t s);
 ro_status validate_frame(const ro_octree *t, const ro_frame_desc *fd, const float *rgba);

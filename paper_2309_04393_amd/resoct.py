@@ -104,6 +104,7 @@ _sig("ro_octree_query", c_i32, [c_vp, _P(OctreeDesc), _P(OctreeSizes)])
 _sig("ro_octree_create", c_i32, [c_vp, _P(OctreeDesc), _P(OctreeBuffers), c_vp, _P(c_vp)])
 _sig("ro_octree_destroy", None, [c_vp])
 _sig("ro_octree_set_leaf_metadata", c_i32, [c_vp, c_u32, c_vp, c_vp])
+_sig("ro_octree_leaf_metadata_from_bricks", c_i32, [c_vp, c_u32, c_vp, c_vp])
 _sig("ro_update_residency", c_i32, [c_vp, c_vp])
 _sig("ro_rebuild_residency", c_i32, [c_vp, c_vp])
 _sig("ro_render", c_i32, [c_vp, _P(FrameDesc), c_vp, c_vp])
@@ -305,6 +306,12 @@ class Octree:
         assert leaf_mm.numel() == 2 * self.n_leaves
         _check(_lib.ro_octree_set_leaf_metadata(self.h, channel, _dev_ptr(leaf_mm), _stream(stream)),
                "ro_octree_set_leaf_metadata")
+
+    def leaf_metadata_from_bricks(self, ids, stream=None):
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        _check(_lib.ro_octree_leaf_metadata_from_bricks(self.h, len(ids), _np_ptr(ids),
+                                                        _stream(stream)),
+               "ro_octree_leaf_metadata_from_bricks")
 
     def update_residency(self, stream=None):
         _check(_lib.ro_update_residency(self.h, _stream(stream)), "ro_update_residency")

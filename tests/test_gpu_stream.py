@@ -196,3 +196,46 @@ def test_render_between_upload_and_residency_update(cells):
     p.check_masks()  # the residency update
     res = p.frame(3, cams[1], 64, 64, 0.5, chans)
     p.check_frame(res, "after-update")
+
+
+def test_leaf_metadata_from_bricks(cells):
+    """Sec. 5.3, metadata computed on the client from brick voxels: with
+    every leaf first unknown ([0, 65535]), metadata derived from resident
+    bricks of level 0 (part of two channels) and level 2 (every channel)
+    equal the oracle's node metadata bit for bit; a frame rendered with them
+    matches the oracle; bad calls change nothing."""
+    from paper_2309_04393_amd import resoct
+    p = Pair(cells, 32, (16, 16, 4), 5, n_slots=700, max_batch=256)
+    n_leaves = p.leaf_mm.shape[1]
+    unknown = np.zeros((cells.n_channels, n_leaves, 2), np.uint16)
+    unknown[..., 1] = 65535
+    for c in range(cells.n_channels):
+        p.gpu.set_metadata(c, unknown[c])
+    _, _, nb = oracle.level_info(p.V)
+    l0 = [oracle.brick_id(p.V.n_levels, c, 0, x, y, 0) for c in (0, 2) for y in range(nb[0][1])
+          for x in range(min(8, nb[0][0]))]
+    l2 = [int(i) for i in p.gpu.all_ids(levels=[2])]
+    ids = np.array(l2[::-1] + l0, np.uint32)
+    assert len(ids) <= 700
+    p.upload(0, ids)
+    p.check_masks()
+    before = p.gpu.tree.meta()
+    missing = [i for i in p.gpu.all_ids(levels=[1])][:1]
+    with pytest.raises(resoct.ResoctError) as e:
+        p.gpu.tree.leaf_metadata_from_bricks(np.array(list(ids[:3]) + missing, np.uint32))
+    assert e.value.code == -5
+    with pytest.raises(resoct.ResoctError) as e:
+        p.gpu.tree.leaf_metadata_from_bricks(np.array([ids[0], 0x00FF0000], np.uint32))
+    assert e.value.code == -1
+    torch.cuda.synchronize()
+    assert np.array_equal(p.gpu.tree.meta(), before)
+    p.gpu.tree.leaf_metadata_from_bricks(ids)
+    torch.cuda.synchronize()
+    ref = oracle.leaf_meta_from_bricks(p.V, cells.levels, unknown, ids)
+    got = p.gpu.tree.meta()
+    want = oracle.meta_all(p.V, ref)
+    assert np.array_equal(got, want), f"metadata differ at {np.argwhere(got != want)[:5]}"
+    p.leaf_mm = ref
+    cam = synth.orbit_path(cells.dims, cells.spacing, 3)[1]
+    res = p.frame(1, cam, 80, 80, 0.5, _chans(4))
+    p.check_frame(res, "meta-from-bricks")
