@@ -166,6 +166,19 @@ ro_status ro_read_requests(ro_cache *c, uint32_t cap, uint32_t *ids_host, uint32
 ro_status ro_read_usage(ro_cache *c, uint32_t frame, uint32_t cap, uint32_t *slots_host,
                         uint32_t *n_out, void *stream);
 
+/* Run-time channel exchange (Sec. 5.2: when another data channel takes a
+ * cache channel's place, what the cache holds for the old one is no longer
+ * valid).  Every resident brick of cache channel `channel` leaves the cache:
+ * its page-table entry is cleared and its slot becomes free (free slots are
+ * taken first, in ascending index, by later uploads); the bricks join the
+ * set awaiting ro_update_residency.  The caller then gives the channel the
+ * new data's metadata (or [0, max] for unknown leaves), runs the residency
+ * update and uploads the new bricks under the same channel's IDs.  Frames
+ * rendered before the residency update read nothing of the channel's old
+ * bricks (the page tables are already cleared).  RO_E_ARG if the channel is
+ * out of range.  Queues one kernel; the host mirrors change at once. */
+ro_status ro_cache_evict_channel(ro_cache *c, uint32_t channel, void *stream);
+
 /* Copy of the host mirror of the page table: brick index -> slot
  * (0xFFFFFFFF when not resident), `count` entries from ro_volume_brick_count. */
 ro_status ro_cache_page_table_host(const ro_cache *c, uint32_t *out, uint64_t count);

@@ -326,6 +326,7 @@ class CacheSim:
         self.total = brick_count(V)
         self.ids = dense_ids(V)
         self.id_to_dense = {int(x): i for i, x in enumerate(self.ids)}
+        self.per_channel = self.total // V.n_channels
         self.res_slot = np.full(self.total, -1, np.int32)
         self.slot_brick = np.full(n_slots, -1, np.int64)
         self.stamp = np.zeros(n_slots, np.uint32)
@@ -346,6 +347,16 @@ class CacheSim:
                              frame_no, n, _p(up), _p(flags), _p(ev), _p(so))
         assert rc == 0
         return flags[:n], ev[:n], so[:n]
+
+    def evict_channel(self, c: int):
+        """Sec. 5.2 channel exchange: every resident brick of cache channel c
+        leaves the cache and its slot becomes free (dense indices are
+        channel-major: channel c owns [c P, (c + 1) P))."""
+        for s in range(self.S):
+            b = int(self.slot_brick[s])
+            if b >= 0 and b // self.per_channel == c:
+                self.res_slot[b] = -1
+                self.slot_brick[s] = -1
 
     def touch(self, frame_no: int, used: np.ndarray):
         """Usage recorded by a frame: stamp = frame for every slot read."""

@@ -260,6 +260,12 @@ extern "C" ro_status ro_cache_create(const ro_volume *v, const ro_cache_desc *d,
 
 extern "C" void ro_cache_destroy(ro_cache *c) { delete c; }
 
+extern "C" ro_status ro_cache_evict_channel(ro_cache *c, uint32_t channel, void *stream) {
+    RO_CHECK(c, RO_E_ARG, "null cache");
+    RO_CHECK(channel < (uint32_t)c->vol->g.m, RO_E_ARG, "channel %u out of range", channel);
+    return cache_evict_channel(c, channel, (hipStream_t)stream);
+}
+
 extern "C" ro_status ro_cache_page_table_host(const ro_cache *c, uint32_t *out, uint64_t count) {
     RO_CHECK(c && out, RO_E_ARG, "null argument");
     RO_CHECK(count == c->pt_host.size(), RO_E_ARG, "count must equal the brick count");

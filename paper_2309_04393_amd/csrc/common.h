@@ -143,6 +143,7 @@ ro_status read_requests_device(ro_cache *c, uint32_t cap, uint32_t *ids, uint32_
                                uint32_t *n_unique, uint64_t *total, hipStream_t s);
 ro_status compact_dense(ro_cache *c, uint32_t *arr, uint32_t cap, uint32_t *ids, uint32_t *vals,
                         uint32_t *n_unique, uint64_t *total, hipStream_t s);
+ro_status cache_evict_channel(ro_cache *c, uint32_t ch, hipStream_t s);
 ro_status read_usage_device(ro_cache *c, uint32_t frame, uint32_t cap, uint32_t *slots,
                             uint32_t *n_out, hipStream_t s);
 

@@ -455,4 +455,37 @@ ro_status stream_bricks_device(ro_cache *c, uint32_t frame, uint32_t n_new, uint
     return RO_OK;
 }
 
+
+// Every resident brick whose dense index lies in [lo, hi) leaves the cache:
+// its page-table entry and its slot's brick are cleared, so the slot is free.
+__global__ void k_evict_range(uint32_t *__restrict__ slot_brick, uint32_t *__restrict__ pt, uint32_t S,
+                              uint32_t lo, uint32_t hi) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    const uint32_t b = slot_brick[i];
+    if (b != kInvalid && b >= lo && b < hi) {
+        pt[b] = kInvalid;
+        slot_brick[i] = kInvalid;
+    }
+}
+
+ro_status cache_evict_channel(ro_cache *c, uint32_t ch, hipStream_t s) {
+    const VolGeo &g = c->vol->g;
+    const uint32_t lo = ch * g.per_channel, hi = lo + g.per_channel;
+    const uint32_t S = c->desc.n_slots;
+    hipLaunchKernelGGL(k_evict_range, dim3((S + 255) / 256), dim3(256), 0, s, c->b.slot_brick, c->b.page_table, S,
+                       lo, hi);
+    RO_HIP(hipGetLastError());
+    // the host mirrors follow; the evicted bricks await the residency update
+    for (uint32_t i = 0; i < S; ++i) {
+        const uint32_t b = c->slot_host[i];
+        if (b != kInvalid && b >= lo && b < hi) {
+            c->pt_host[b] = kInvalid;
+            c->slot_host[i] = kInvalid;
+            c->dirty.push_back(b);
+        }
+    }
+    return RO_OK;
+}
+
 }  // namespace ro

@@ -16,10 +16,15 @@ from . import resoct
 
 class GpuScene:
     def __init__(self, src, brick: int, leaf, depth: int, n_slots: int, max_batch: int = 4096,
-                 start_level: int = 0, device="cuda", set_metadata=True):
+                 start_level: int = 0, device="cuda", set_metadata=True, cache_channels=None):
         self.src = src
         self.device = device
-        self.vol = resoct.Volume(src.dims, src.spacing, src.n_channels, 1 if src.bits == 8 else 2,
+        m = src.n_channels if cache_channels is None else int(cache_channels)
+        assert 1 <= m <= src.n_channels
+        # cache channel c holds the source's channel channel_map[c] (Sec. 5.2:
+        # the octree and page tables reference m of the n channels at a time)
+        self.channel_map = list(range(m))
+        self.vol = resoct.Volume(src.dims, src.spacing, m, 1 if src.bits == 8 else 2,
                                  brick, src.n_levels)
         self.cache = resoct.Cache(self.vol, n_slots, max_batch, device=device)
         self.tree = resoct.Octree(self.cache, leaf, depth, start_level, device=device)
@@ -29,14 +34,31 @@ class GpuScene:
         self.ldims, self.lf, self.nb = self.vol.levels()
         self.np_dtype = np.uint8 if src.bits == 8 else np.uint16
         if set_metadata:
-            for c in range(src.n_channels):
-                self.set_metadata(c, src.leaf_minmax(c, self.leaf, self.tree.leaf_grid))
+            for c in range(m):
+                self.set_metadata(c, src.leaf_minmax(self.channel_map[c], self.leaf, self.tree.leaf_grid))
 
     def set_metadata(self, c, leaf_mm: np.ndarray):
         t = torch.from_numpy(np.ascontiguousarray(leaf_mm, dtype=np.uint16).reshape(-1).view(np.int16))
         t = t.to(self.device).view(torch.uint16)
         self.tree.set_leaf_metadata(c, t)
         torch.cuda.current_stream().synchronize()
+
+    def exchange_channel(self, c: int, src_channel: int, metadata: str = "server"):
+        """Run-time channel exchange (Sec. 5.2): cache channel c now holds the
+        source's channel src_channel.  The old channel's bricks leave the
+        cache, the channel gets the new data's metadata ("server") or unknown
+        leaves ("unknown": [0, max raw value], refined later from bricks),
+        and the residency masks are updated; the new bricks arrive through
+        the usual request-driven uploads."""
+        self.cache.evict_channel(c)
+        self.channel_map[c] = int(src_channel)
+        if metadata == "server":
+            mm = self.src.leaf_minmax(int(src_channel), self.leaf, self.tree.leaf_grid)
+        else:
+            mm = np.zeros((self.tree.n_leaves, 2), np.uint16)
+            mm[:, 1] = 255 if self.src.bits == 8 else 65535
+        self.set_metadata(c, mm)
+        self.tree.update_residency()
 
     # ------------------------------------------------------------- bricks
     def all_ids(self, channels=None, levels=None):
@@ -57,7 +79,8 @@ class GpuScene:
         stride = self.cache.slot_stride
         host = np.zeros((max(n, 1), stride), np.uint8)
         nbytes = self.E ** 3 * (1 if self.np_dtype == np.uint8 else 2)
-        dec = [self.vol.decode(int(i)) for i in ids]
+        # (source channel, level, brick) of each ID
+        dec = [(self.channel_map[c], l, b) for c, l, b in (self.vol.decode(int(i)) for i in ids)]
         if hasattr(self.src, "bricks_multi"):
             # one generator pass per brick position serves every channel there
             groups = {}

@@ -96,6 +96,7 @@ _sig("ro_cache_destroy", None, [c_vp])
 _sig("ro_stream_bricks", c_i32, [c_vp, c_u32, c_u32, c_vp, c_vp, c_vp, c_vp])
 _sig("ro_read_requests", c_i32, [c_vp, c_u32, c_vp, c_vp, _P(c_u32), _P(c_u64), c_vp])
 _sig("ro_read_usage", c_i32, [c_vp, c_u32, c_u32, c_vp, _P(c_u32), c_vp])
+_sig("ro_cache_evict_channel", c_i32, [c_vp, c_u32, c_vp])
 _sig("ro_cache_page_table_host", c_i32, [c_vp, c_vp, c_u64])
 _sig("ro_cache_state_size", c_i32, [c_vp, _P(c_sz)])
 _sig("ro_cache_save_state", c_i32, [c_vp, c_vp, c_sz])
@@ -267,6 +268,9 @@ class Cache:
     def load_state(self, blob: np.ndarray):
         blob = np.ascontiguousarray(blob, dtype=np.uint8)
         _check(_lib.ro_cache_load_state(self.h, _np_ptr(blob), blob.size), "ro_cache_load_state")
+
+    def evict_channel(self, channel: int, stream=None):
+        _check(_lib.ro_cache_evict_channel(self.h, channel, _stream(stream)), "ro_cache_evict_channel")
 
     def page_table_host(self) -> np.ndarray:
         out = np.zeros(self.n_bricks, np.uint32)

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from tests.helpers import compare_images, compare_requests, compare_usage, gpu_rgba
+from tests.helpers import compare_images, compare_requests, compare_usage, gpu_rgba, leaf_grid
 
 pytestmark = pytest.mark.gpu
 
@@ -239,3 +239,65 @@ def test_leaf_metadata_from_bricks(cells):
     cam = synth.orbit_path(cells.dims, cells.spacing, 3)[1]
     res = p.frame(1, cam, 80, 80, 0.5, _chans(4))
     p.check_frame(res, "meta-from-bricks")
+
+
+def test_channel_exchange():
+    """Sec. 5.2 run-time channel exchange with a cache that references 3 of
+    a source's 5 channels: cache channel 1 changes from source channel 1 to
+    4.  Its bricks leave (page tables equal the oracle's, freed slots are
+    taken first by the next uploads), the masks follow, and frames before and
+    after the new bricks arrive match the oracle on the new channel's data."""
+    from paper_2309_04393_amd.pipeline import GpuScene
+    src = _cells(dims=(256, 256, 32), n_ch=5, n_levels=5, seed=7)
+    B, leaf, depth, S = 32, (16, 16, 4), 4, 260
+    g = GpuScene(src, B, leaf, depth, S, max_batch=256, cache_channels=3)
+    V = oracle.make_volume(src.dims, src.spacing, 3, src.bits, B, src.n_levels, leaf, depth)
+    sim = oracle.CacheSim(V, S)
+    dense = oracle.dense_ids(V)
+    lg = leaf_grid(src.dims, leaf, depth)
+    chans = _chans(3, hi=4)
+    cam = synth.orbit_path(src.dims, src.spacing, 3)[1]
+
+    def upload(f, ids):
+        fg = g.upload(f, ids)
+        fo, _, _ = sim.stream(f, sim.dense_of(ids))
+        assert np.array_equal(fg, fo), "upload flags differ"
+        pt = g.cache.page_table_host()
+        assert {int(i): int(s) for i, s in zip(dense, pt) if s != 0xFFFFFFFF} == sim.page_table()
+
+    def frame(f, name):
+        r = g.render(f, cam, 72, 72, 0.5, chans)
+        torch.cuda.synchronize()
+        ids, cnt, nu, tot = g.cache.read_requests(1 << 20)
+        used, _ = g.cache.read_usage(f)
+        fr, _ = oracle.make_frame(cam, 72, 72, 0.5, chans, term_margin=1e-6)
+        levels = [src.levels[s] for s in g.channel_map]
+        mm = np.stack([src.leaf_minmax(s, leaf, lg) for s in g.channel_map])
+        o = oracle.render(V, levels, sim.res_slot, mm, fr, S)
+        sim.touch(f, o["used"])
+        st = compare_images(gpu_rgba(r["rgba"], 72, 72), o["rgba"], o["amb_pix"])
+        compare_requests(ids, cnt, o["counts"], o["amb_counts"], dense)
+        compare_usage(used, o["used"], o["amb_used"])
+        _report(name, requests=nu, **st)
+        return ids, cnt
+
+    ids = g.all_ids(levels=[1, 2, 3, 4])
+    upload(0, ids[:S - 20])
+    g.tree.update_residency()
+    frame(1, "exchange-before")
+    old = {int(i): int(s) for i, s in zip(dense, g.cache.page_table_host()) if s != 0xFFFFFFFF}
+    g.exchange_channel(1, 4)
+    sim.evict_channel(1)
+    torch.cuda.synchronize()
+    pt = g.cache.page_table_host()
+    now = {int(i): int(s) for i, s in zip(dense, pt) if s != 0xFFFFFFFF}
+    assert now == sim.page_table()
+    assert len(now) < len(old) and all(old[i] == s for i, s in now.items())
+    assert np.array_equal(g.tree.masks(), oracle.masks(V, sim.res_slot))
+    ids, cnt = frame(2, "exchange-no-bricks")  # channel 1 contributes nothing yet and requests its bricks
+    assert np.any((ids >> 24) // src.n_levels == 1)
+    order = np.lexsort((ids, -cnt.astype(np.int64)))
+    upload(3, ids[order][:200])
+    g.tree.update_residency()
+    assert np.array_equal(g.tree.masks(), oracle.masks(V, sim.res_slot))
+    frame(4, "exchange-after")
