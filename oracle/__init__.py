@@ -50,7 +50,8 @@ class Frame(ctypes.Structure):
                 ("vis", ctypes.c_int * MAXC), ("lod_lo", ctypes.c_int * MAXC),
                 ("lod_hi", ctypes.c_int * MAXC), ("W0", ctypes.c_uint32 * MAXC),
                 ("W1", ctypes.c_uint32 * MAXC), ("tf", ctypes.c_void_p * MAXC),
-                ("term_alpha", ctypes.c_double), ("term_margin", ctypes.c_double), ("adaptive", ctypes.c_int)]
+                ("term_alpha", ctypes.c_double), ("term_margin", ctypes.c_double), ("adaptive", ctypes.c_int),
+                ("homogeneous", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -85,6 +86,8 @@ def lib():
         L.or_masks.argtypes = [PV, vp, vp]
         L.or_tf_empty.restype = ci
         L.or_tf_empty.argtypes = [ctypes.c_uint32] * 4 + [vp]
+        L.or_tf_flat.restype = ci
+        L.or_tf_flat.argtypes = [ctypes.c_uint32] * 4 + [vp]
         L.or_render.restype = ci
         L.or_render.argtypes = [PV, vp, vp, vp, vp, vp, ctypes.POINTER(Frame), ci, ci, vp, vp, vp, vp,
                                 vp, vp, vp, ctypes.POINTER(Stats), ci]
@@ -212,8 +215,13 @@ def tf_empty(mn, mx, W0, W1, tf) -> bool:
     return bool(lib().or_tf_empty(mn, mx, W0, W1, _p(t)))
 
 
+def tf_flat(mn, mx, W0, W1, tf) -> bool:
+    t = np.ascontiguousarray(tf, dtype=np.float32)
+    return bool(lib().or_tf_flat(mn, mx, W0, W1, _p(t)))
+
+
 def make_frame(cam: dict, W, H, delta, channels: list, term_alpha=0.99, lod_bias=1.0,
-               term_margin=1e-5, adaptive=False):
+               term_margin=1e-5, adaptive=False, homogeneous=False):
     """channels: list of dicts {c, lo, hi, W0, W1, tf (256x4 float32)} in
     visible-slot order.  Returns (Frame, keepalive)."""
     fr = Frame()
@@ -227,6 +235,7 @@ def make_frame(cam: dict, W, H, delta, channels: list, term_alpha=0.99, lod_bias
     fr.delta, fr.lod_bias, fr.term_alpha = delta, lod_bias, term_alpha
     fr.term_margin = term_margin
     fr.adaptive = 1 if adaptive else 0
+    fr.homogeneous = 1 if homogeneous else 0
     fr.nvis = len(channels)
     keep = []
     for j, ch in enumerate(channels):

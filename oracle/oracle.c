@@ -314,6 +314,30 @@ int or_tf_empty(uint32_t mn, uint32_t mx, uint32_t W0, uint32_t W1, const float 
     return 1;
 }
 
+/* Homogeneity of a [mn, mx] raw range (Alg. 1 isHomogeneous, read through
+ * the transfer function): the interpolated RGBA is the same for every value
+ * in [mn, mx], with alpha non-zero.  A single value (mn == mx) always is
+ * (alpha aside); a wider range is iff every table entry reachable from it
+ * (the same set as for emptiness) holds the same RGBA, since the table is
+ * interpolated linearly between entries.  Then the value mn stands for
+ * every sample, and a sample there needs no voxel.  Exact integer
+ * arithmetic. */
+int or_tf_flat(uint32_t mn, uint32_t mx, uint32_t W0, uint32_t W1, const float *tf /*256x4*/) {
+    if (mn == mx) return !or_tf_empty(mn, mx, W0, W1, tf);
+    long long den = (long long)W1 - (long long)W0;
+    long long nlo = 255LL * ((long long)mn * 256 - (long long)W0);
+    long long nhi = 255LL * ((long long)mx * 256 - (long long)W0);
+    long long lo = nlo <= 0 ? 0 : nlo / den;
+    long long hi = nhi <= 0 ? 0 : (nhi + den - 1) / den;
+    if (lo > 255) lo = 255;
+    if (hi > 255) hi = 255;
+    if (tf[4 * lo + 3] == 0.0f) return 0;
+    for (long long e = lo + 1; e <= hi; ++e)
+        for (int k = 0; k < 4; ++k)
+            if (tf[4 * e + k] != tf[4 * lo + k]) return 0;
+    return 1;
+}
+
 static void tf_eval(double v, uint32_t W0, uint32_t W1, const float *tf, double out[4]) {
     double w0 = W0 / 256.0, w1 = W1 / 256.0;
     double x = (v - w0) / (w1 - w0);
@@ -345,6 +369,7 @@ typedef struct {
     double term_alpha;
     double term_margin; /* |A - term_alpha| below this marks an ambiguous termination */
     int adaptive;       /* LOD-adaptive step (Sec. 6.1, the sampling distance grows with the level) */
+    int homogeneous;    /* homogeneous leaves rendered from their metadata (Alg. 1 renderAndSkipNode) */
 } or_frame;
 
 /* Level data: lvl[c * L + l] points to the level's array [z][y][x]
@@ -638,6 +663,17 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
                         int c = Fr->vis[jv];
                         const uint16_t *mm = leaf_mm + ((long long)c * nleaf + leaf) * 2;
                         if (or_tf_empty(mm[0], mm[1], Fr->W0[jv], Fr->W1[jv], Fr->tf[jv])) continue;
+                        if (Fr->homogeneous && or_tf_flat(mm[0], mm[1], Fr->W0[jv], Fr->W1[jv], Fr->tf[jv])) {
+                            /* the leaf's value stands for the sample: no brick,
+                             * no request, no read, whatever is resident */
+                            if (shadow) continue;
+                            double rgbaH[4];
+                            tf_eval((double)mm[0], Fr->W0[jv], Fr->W1[jv], Fr->tf[jv], rgbaH);
+                            prod *= (1.0 - rgbaH[3]);
+                            sa += rgbaH[3];
+                            for (int k2 = 0; k2 < 3; ++k2) srgb[k2] += rgbaH[3] * rgbaH[k2];
+                            continue;
+                        }
                         int ls = nlev;
                         if (ls < Fr->lod_lo[jv]) ls = Fr->lod_lo[jv];
                         if (ls > Fr->lod_hi[jv]) ls = Fr->lod_hi[jv];
