@@ -282,6 +282,7 @@ ro_status ro_rebuild_residency(ro_octree *t, void *stream);
 #define RO_RENDER_NO_SKIP 1u /* evaluate every sample (results are identical) */
 #define RO_RENDER_AOV 2u     /* write per-pixel per-level sample counts to aov_dev */
 #define RO_RENDER_ADAPTIVE_STEP 4u /* LOD-adaptive sampling distance (see below) */
+#define RO_RENDER_HOMOGENEOUS 8u   /* homogeneous leaves rendered from their metadata (see below) */
 
 /* One frame (Sec. 6.1, Alg. 1; Sec. 6.2).  Pixel (i, j), row 0 at the top,
  * has a = (2i+1-W)/W, b = (H-2j-1)/H.  Orthographic: origin
@@ -312,7 +313,17 @@ ro_status ro_rebuild_residency(ro_octree *t, void *stream);
  * channels, and r its x factor (a power of two).  The sample is evaluated
  * only when k is a multiple of r (so skipping resumes on the same grid), and
  * its mixed opacity becomes 1 - (1 - alpha)^r with the premultiplied colour
- * scaled by the same factor.  Where l_s = 0 the frame is unchanged. */
+ * scaled by the same factor.  Where l_s = 0 the frame is unchanged.
+ * RO_RENDER_HOMOGENEOUS (Alg. 1 isHomogeneous / renderAndSkipNode, read
+ * through the transfer function): a channel whose leaf is not empty and
+ * whose interpolated table gives one RGBA for every value in the leaf's
+ * [min, max] (a single value always does; a wider range when every table
+ * entry reachable from it is identical) is sampled as the value min: it
+ * reads no brick, requests nothing and stamps no slot, whatever is resident
+ * and whatever level is desired.  Samples stay on the same grid and are
+ * composited one by one, so early termination is unchanged.  Where level 0
+ * is read and the metadata are exact, the image is the same as without the
+ * option. */
 typedef struct {
     uint32_t frame;     /* frame number written into slot stamps, < 0xFFFFFFFF */
     int32_t projection; /* RO_PROJ_ORTHO or RO_PROJ_PERSP */

@@ -560,7 +560,8 @@ ro_status validate_frame(const ro_octree *t, const ro_frame_desc *fd, const floa
     RO_CHECK(fd->term_alpha > 0.0f && fd->term_alpha <= 1.0f, RO_E_ARG, "term_alpha not in (0, 1]");
     RO_CHECK(fd->frame != kInvalid, RO_E_ARG, "frame 0xFFFFFFFF is reserved");
     RO_CHECK(fd->start_level >= -1 && fd->start_level <= t->t.depth, RO_E_ARG, "bad start_level");
-    RO_CHECK(!(fd->flags & ~(RO_RENDER_NO_SKIP | RO_RENDER_AOV | RO_RENDER_ADAPTIVE_STEP)), RO_E_ARG,
+    RO_CHECK(!(fd->flags & ~(RO_RENDER_NO_SKIP | RO_RENDER_AOV | RO_RENDER_ADAPTIVE_STEP | RO_RENDER_HOMOGENEOUS)),
+             RO_E_ARG,
              "unknown render flags 0x%x", fd->flags);
     RO_CHECK(!(fd->flags & RO_RENDER_AOV) || fd->aov_dev, RO_E_ARG, "AOV requested without buffer");
     uint32_t seen = 0;

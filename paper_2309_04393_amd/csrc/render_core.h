@@ -48,7 +48,7 @@ struct RenderArgs {
 };
 
 struct ChanLds {
-    int c, lo, hi, nruns;
+    int c, lo, hi, nruns, nflat;
     float w0, iw;
     uint32_t ehi;     // one zero-opacity run starting at raw value 0: its last raw value, else ~0
     uint32_t single;  // same in every entry: every visible channel has such a run
@@ -94,6 +94,45 @@ __device__ inline int build_runs(const float4 *tf, uint32_t W0, uint32_t W1, uin
 
 __device__ __forceinline__ bool range_empty(uint32_t mm, const uint32_t *runs, int nr) {
     const uint32_t mn = mm & 0xFFFFu, mx = mm >> 16;
+    for (int r = 0; r < nr; ++r) {
+        const uint32_t q = runs[r];
+        if (mn >= (q & 0xFFFFu) && mx <= (q >> 16)) return true;
+    }
+    return false;
+}
+
+// Runs of identical, non-zero-alpha table entries as raw-value bounds
+// (lo | hi << 16, the same window arithmetic as build_runs): a range
+// [mn, mx] with mn < mx gives one interpolated RGBA iff some run has
+// mn >= lo and mx <= hi.  Only runs of two or more entries and single
+// entries at either end can hold such a range (a strictly increasing table
+// position is constant only where it is clamped), so at most 129 are kept.
+constexpr int kMaxFlat = 130;
+__device__ inline int build_flat_runs(const float4 *tf, uint32_t W0, uint32_t W1, uint32_t *runs) {
+    int n = 0, e = 0;
+    const uint64_t den = (uint64_t)W1 - (uint64_t)W0;
+    while (e < 256) {
+        const float4 t = tf[e];
+        const int a = e;
+        while (e + 1 < 256 && tf[e + 1].x == t.x && tf[e + 1].y == t.y && tf[e + 1].z == t.z &&
+               tf[e + 1].w == t.w)
+            ++e;
+        const int b = e++;
+        if (t.w == 0.0f || (a == b && a != 0 && a != 255)) continue;
+        uint64_t rlo = a == 0 ? 0 : (255ull * W0 + (uint64_t)a * den + 65279ull) / 65280ull;
+        uint64_t rhi = b == 255 ? 65535ull : (255ull * W0 + (uint64_t)b * den) / 65280ull;
+        if (rhi > 65535ull) rhi = 65535ull;
+        if (rlo <= rhi && n < kMaxFlat) runs[n++] = (uint32_t)rlo | ((uint32_t)rhi << 16);
+    }
+    return n;
+}
+
+// Homogeneity of a non-empty channel's [min, max] (frame option
+// RO_RENDER_HOMOGENEOUS): one interpolated RGBA over the whole range.  A
+// single value always qualifies.
+__device__ __forceinline__ bool range_flat(uint32_t mm, const uint32_t *runs, int nr) {
+    const uint32_t mn = mm & 0xFFFFu, mx = mm >> 16;
+    if (mn == mx) return true;
     for (int r = 0; r < nr; ++r) {
         const uint32_t q = runs[r];
         if (mn >= (q & 0xFFFFu) && mx <= (q >> 16)) return true;
@@ -272,12 +311,14 @@ __host__ __device__ constexpr size_t slot_bytes(int e, int bpv) {
 
 // EC: the brick edge with halo known at compile time (0: read from A).  A
 // constant edge turns the four gather offsets into instruction immediates.
-// ADAPT: whether the LOD-adaptive step is compiled in (frames that ask for it
-// go to a kernel that has it).
-template <int NV, int BPV, bool AOV, int EC, bool ADAPT, class Source>
+// ADAPT / HOMOG: whether the LOD-adaptive step / homogeneous leaves are
+// compiled in (frames that ask for them go to a kernel that has them; with
+// HOMOG, s_flat holds each channel's runs of identical table entries).
+template <int NV, int BPV, bool AOV, int EC, bool ADAPT, bool HOMOG, class Source>
 __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, const float4 *s_tf,
                                             const ChanLds *s_ch, const uint32_t *s_runs, const LevLds *s_lv,
-                                            const NodeLds *s_nd, uint32_t stats[6], LdsSlots slot) {
+                                            const NodeLds *s_nd, const uint32_t *s_flat, uint32_t stats[6],
+                                            LdsSlots slot) {
     const int nvis = A.nvis;
     const int D = A.depth;
     const int L = A.L;
@@ -288,6 +329,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     const int s0 = A.start_level;
     const bool noskip = (A.flags & RO_RENDER_NO_SKIP) != 0;
     const bool adaptive = ADAPT && (A.flags & RO_RENDER_ADAPTIVE_STEP) != 0;
+    const bool homog = HOMOG && (A.flags & RO_RENDER_HOMOGENEOUS) != 0;
     const NodeLds leafl = s_nd[D];
     const bool single = s_ch[0].single != 0;
     uint32_t st_samples = 0, st_reads = 0, st_miss = 0, st_visits = 0, st_nonempty = 0, st_iters = 0;
@@ -304,6 +346,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     uint32_t cur_leaf = kInvalid;
     int cur_lod = -1, lod = 0;
     uint32_t emask = 0, missmask = 0;
+    uint32_t hmask = 0;  // channels homogeneous in the current leaf: sampled from its metadata
     uint64_t lvpack = 0;
     uint32_t nvisit = 0;
     int lc[3] = {-1, -1, -1};  // L0 origin of the last visited leaf (none yet)
@@ -372,6 +415,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         rpace = 0;
         while (lod + 1 < L && (unsigned long long)k >= s_lv[lod + 1].K) ++lod;
         emask = missmask = 0;
+        hmask = 0;
         lvpack = 0;
         nvisit = 0;
         lc[0] = lc[1] = lc[2] = -1;
@@ -511,7 +555,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     const uint32_t node = node_at(nd, iu[0] >> field(nd.nsh, 0), iu[1] >> field(nd.nsh, 1),
                                                   iu[2] >> field(nd.nsh, 2));
                     // the node's metadata, kGroup channels per batch of loads
-                    uint32_t em = 0;
+                    uint32_t em = 0, hm = 0;
                     const uint32_t *nm = A.meta + (size_t)node * m;
 #pragma unroll
                     for (int g = 0; g < NV; g += kGroup) {
@@ -544,7 +588,20 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                         }
                         asm volatile("" ::: "memory");
                     }
-                    if (dl == D) emask = em;
+                    if (homog && dl == D) {
+                        // the leaf's non-empty channels, one at a time (a
+                        // rolled loop keeps the unrolled metadata loads' registers free)
+                        uint32_t cand = vismask & ~em;
+                        while (cand) {
+                            const int j = __builtin_ctz(cand);
+                            cand &= cand - 1u;
+                            if (range_flat(nm[s_ch[j].c], s_flat + j * kMaxFlat, s_ch[j].nflat)) hm |= 1u << j;
+                        }
+                    }
+                    if (dl == D) {
+                        emask = em;
+                        hmask = hm;
+                    }
                     if (em == (1u << nvis) - 1u && !noskip) {
                         double te = INFINITY;
 #pragma unroll
@@ -595,7 +652,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 all_at = ((andm >> lsu) & 1u) != 0;
             }
             if (all_at) {
-                look = vismask & ~emask;
+                look = vismask & ~emask & ~hmask;
                 lvpack = 0;
 #pragma unroll
                 for (int j = 0; j < NV; ++j)
@@ -618,7 +675,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 #pragma unroll
                     for (int jj = 0; jj < kGroup; ++jj) {
                         const int j = g + jj;
-                        if (j < nvis && !((emask >> j) & 1u)) {
+                        if (j < nvis && !(((emask | hmask) >> j) & 1u)) {
                             const ChanLds ch = s_ch[j];
                             const int ls = min(max(lod, ch.lo), ch.hi);
                             const uint32_t mj = mk[jj] >> ls;
@@ -719,7 +776,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 #pragma unroll
             for (int jj = 0; jj < kGroup; ++jj) {
                 const int j = g + jj;
-                ok[jj] = j < nvis && slot[j] != kInvalid;
+                ok[jj] = j < nvis && slot[j] != kInvalid && !(homog && ((hmask >> j) & 1u));
                 const int lu = (int)((lvpack >> (4 * j)) & 15u);
                 if (ok[jj] && lu != lprev) {
                     const LevLds lv = s_lv[lu];
@@ -755,20 +812,30 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 #pragma unroll
             for (int jj = 0; jj < kGroup; ++jj) {
                 const int j = g + jj;
-                if (!ok[jj]) continue;
-                const float f0 = fq[jj][0], f1 = fq[jj][1], f2 = fq[jj][2];
-                float v00[2], v10[2], v01[2], v11[2];
-                unpack<BPV>(w[jj][0], v00);
-                unpack<BPV>(w[jj][1], v10);
-                unpack<BPV>(w[jj][2], v01);
-                unpack<BPV>(w[jj][3], v11);
-                const float c00 = v00[0] + (v00[1] - v00[0]) * f0;
-                const float c10 = v10[0] + (v10[1] - v10[0]) * f0;
-                const float c01 = v01[0] + (v01[1] - v01[0]) * f0;
-                const float c11 = v11[0] + (v11[1] - v11[0]) * f0;
-                const float e0 = c00 + (c10 - c00) * f1;
-                const float e1 = c01 + (c11 - c01) * f1;
-                const float v = e0 + (e1 - e0) * f2;
+                // a homogeneous channel takes the leaf's minimum (every value
+                // of the leaf's range maps to the same table result)
+                const bool hv = homog && j < nvis && ((hmask >> j) & 1u);
+                if (!ok[jj] && !hv) continue;
+                float v;
+                if (ok[jj]) {
+                    const float f0 = fq[jj][0], f1 = fq[jj][1], f2 = fq[jj][2];
+                    float v00[2], v10[2], v01[2], v11[2];
+                    unpack<BPV>(w[jj][0], v00);
+                    unpack<BPV>(w[jj][1], v10);
+                    unpack<BPV>(w[jj][2], v01);
+                    unpack<BPV>(w[jj][3], v11);
+                    const float c00 = v00[0] + (v00[1] - v00[0]) * f0;
+                    const float c10 = v10[0] + (v10[1] - v10[0]) * f0;
+                    const float c01 = v01[0] + (v01[1] - v01[0]) * f0;
+                    const float c11 = v11[0] + (v11[1] - v11[0]) * f0;
+                    const float e0 = c00 + (c10 - c00) * f1;
+                    const float e1 = c01 + (c11 - c01) * f1;
+                    v = e0 + (e1 - e0) * f2;
+                    ++st_reads;
+                    if (AOV) A.aov[((size_t)py * A.W + px) * L + (int)((lvpack >> (4 * j)) & 15u)] += 1;
+                } else {
+                    v = (float)(A.meta[(size_t)cur_leaf * m + s_ch[j].c] & 0xFFFFu);
+                }
                 const ChanLds ch = s_ch[j];
                 float x = (v - ch.w0) * ch.iw;
                 x = fminf(fmaxf(x, 0.0f), 1.0f);
@@ -782,13 +849,11 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 const float r = ta.x + (tb.x - ta.x) * f;
                 const float gg = ta.y + (tb.y - ta.y) * f;
                 const float bb = ta.z + (tb.z - ta.z) * f;
-                ++st_reads;
                 prod *= 1.0f - al;
                 sa += al;
                 sr += al * r;
                 sg += al * gg;
                 sbl += al * bb;
-                if (AOV) A.aov[((size_t)py * A.W + px) * L + (int)((lvpack >> (4 * j)) & 15u)] += 1;
             }
             // the next group's loads are issued after this group is used:
             // bounds the registers held by loads in flight
@@ -833,7 +898,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 // LDS.  Ends with a workgroup barrier.
 template <int NV>
 __device__ __forceinline__ void stage_frame(const RenderArgs &A, float4 *s_tf, ChanLds *s_ch, uint32_t *s_runs,
-                                            LevLds *s_lv, NodeLds *s_nd) {
+                                            LevLds *s_lv, NodeLds *s_nd, uint32_t *s_flat) {
     const int nvis = A.nvis;
     for (int i = threadIdx.x; i < nvis * 256; i += blockDim.x) s_tf[i] = A.tf[i];
     const unsigned t = threadIdx.x;
@@ -867,7 +932,10 @@ __device__ __forceinline__ void stage_frame(const RenderArgs &A, float4 *s_tf, C
         const uint32_t r0 = s_runs[t * kMaxRuns];
         ch.ehi = (ch.nruns == 1 && (r0 & 0xFFFFu) == 0) ? (r0 >> 16) : 0xFFFFFFFFu;
         ch.single = 0;
+        ch.nflat = 0;
         s_ch[t] = ch;
+        if (s_flat && (A.flags & RO_RENDER_HOMOGENEOUS))
+            s_ch[t].nflat = build_flat_runs(s_tf + t * 256, A.W0[t], A.W1[t], s_flat + t * kMaxFlat);
     }
     __syncthreads();
     if (t < (unsigned)nvis) {

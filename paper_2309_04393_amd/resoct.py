@@ -27,7 +27,7 @@ MAX_CHANNELS = 16
 MAX_LEVELS = 16
 INVALID = 0xFFFFFFFF
 PROJ_ORTHO, PROJ_PERSP = 0, 1
-RENDER_NO_SKIP, RENDER_AOV, RENDER_ADAPTIVE_STEP = 1, 2, 4
+RENDER_NO_SKIP, RENDER_AOV, RENDER_ADAPTIVE_STEP, RENDER_HOMOGENEOUS = 1, 2, 4, 8
 
 c_i32, c_u32, c_u64, c_sz, c_vp, c_dbl = (ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
                                           ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double)

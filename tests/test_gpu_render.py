@@ -69,7 +69,8 @@ class Pair:
         used, nused = self.gpu.cache.read_usage(f)
         fr, keep = oracle.make_frame(cam, W, H, step, chans, term_margin=term_margin,
                                      lod_bias=kw.get("lod_bias", 1.0),
-                                     adaptive=bool(kw.get("flags", 0) & resoct.RENDER_ADAPTIVE_STEP))
+                                     adaptive=bool(kw.get("flags", 0) & resoct.RENDER_ADAPTIVE_STEP),
+                                     homogeneous=bool(kw.get("flags", 0) & resoct.RENDER_HOMOGENEOUS))
         o = oracle.render(self.V, self.src.levels, self.sim.res_slot, self.leaf_mm, fr, self.S, aov=aov)
         self.sim.touch(f, o["used"])
         out = dict(gpu=gpu_rgba(r["rgba"], H, W), ref=o["rgba"], o=o, ids=ids, cnt=cnt, nu=nu, tot=tot,
@@ -294,7 +295,7 @@ def test_render_argument_errors(cfg1):
     unknown flag bits, an empty viewport, an inverted level range."""
     p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
     cam = synth.camera_oblique_ortho((64, 64, 64), (1, 1, 1), 1, 16, 16)
-    for kw, chans, W in ((dict(flags=8), _cfg1_chans(0, 2), 16), ({}, _cfg1_chans(0, 2), 0),
+    for kw, chans, W in ((dict(flags=16), _cfg1_chans(0, 2), 16), ({}, _cfg1_chans(0, 2), 0),
                          ({}, _cfg1_chans(2, 1), 16)):
         with pytest.raises(resoct.ResoctError) as e:
             p.gpu.render(1, cam, W, 16, 0.5, chans, **kw)
@@ -302,3 +303,90 @@ def test_render_argument_errors(cfg1):
     r = p.gpu.render(1, cam, 16, 16, 0.5, _cfg1_chans(0, 2))  # still usable
     torch.cuda.synchronize()
     assert np.isfinite(gpu_rgba(r["rgba"], 16, 16)).all()
+
+
+# ------------------------------------------------- homogeneous leaves (row f2)
+
+def _plateau_chans(lo=0, hi=0):
+    """cfg1 channel whose table is flat from entry 16 up: blob cores are
+    homogeneous leaves (57 of the 470 non-empty ones)."""
+    tf = np.zeros((256, 4), np.float32)
+    tf[:, :3] = (0.9, 0.5, 0.1)
+    tf[:16, 3] = np.linspace(0, 0.08, 16, dtype=np.float32)
+    tf[16:, 3] = np.float32(0.08)
+    W0, W1 = synth.window_fx(0.02 * 255, 0.4 * 255)
+    return [dict(c=0, lo=lo, hi=hi, W0=W0, W1=W1, tf=tf)]
+
+
+def test_homogeneous_leaves_full_residency(cfg1):
+    """Alg. 1 renderAndSkipNode with every brick resident and level 0
+    desired: images, requests and usage match the oracle, and the image is
+    bit-identical to the plain frame (a flat table returns its entry exactly
+    and trilinear weights of equal voxels return the voxel) with fewer brick
+    reads."""
+    p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
+    assert (p.upload(0, p.gpu.all_ids()) == 1).all()
+    p.check_masks()
+    cam = synth.camera_persp((120.0, 95.0, 80.0), (32, 30, 34), (0, 0, 1), 40.0, 1.0)
+    stats = []
+    imgs = []
+    for f, flags in ((1, 0), (2, resoct.RENDER_HOMOGENEOUS)):
+        st = torch.zeros(8, dtype=torch.int64, device="cuda")
+        res = p.frame(f, cam, 96, 96, 0.5, _plateau_chans(), stats=st, flags=flags)
+        p.check_frame(res, f"homog-full-{flags}")
+        stats.append(st.cpu().numpy())
+        imgs.append(res["gpu"])
+    assert np.array_equal(imgs[0], imgs[1])
+    assert stats[1][1] < 0.95 * stats[0][1]  # brick reads
+    assert stats[1][0] == stats[0][0]  # samples
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_homogeneous_leaves_partial_residency(cfg1, seed):
+    """With part of the bricks resident and levels 0..2: homogeneous leaves
+    neither request nor read, whatever is resident; images, request
+    multisets and usage match the oracle."""
+    p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
+    ids = p.gpu.all_ids()
+    p.upload(0, ids[np.random.default_rng(seed).random(len(ids)) < 0.5])
+    p.check_masks()
+    cam = synth.camera_oblique_ortho((64, 64, 64), (1, 1, 1), 2 + seed, 96, 80)
+    res = p.frame(1, cam, 96, 80, 0.5, _plateau_chans(0, 2), lod_bias=0.7, flags=resoct.RENDER_HOMOGENEOUS)
+    p.check_frame(res, f"homog-partial-{seed}")
+
+
+def test_homogeneous_leaves_cells_channels():
+    """Four u16 cell channels with exact leaf metadata (computed from the
+    level-0 data), per-channel ranges and partial residency: channels 0 and 2
+    show a faint haze whose table is flat over the low values (background
+    leaves are homogeneous), 1 and 3 are zero there (empty), so one leaf has
+    empty, homogeneous and sampled channels; images, requests and usage match
+    the oracle."""
+    src = synth.CellVolume((256, 256, 64), 4, spacing=(1, 1, 4), n_levels=5, seed=2)
+    src.levels = [[src.level_array(c, l) for l in range(src.n_levels)] for c in range(4)]
+    p = Pair(src, 32, (16, 16, 4), 4, n_slots=200, max_batch=512)
+    l0 = [int(i) for i in p.gpu.all_ids(levels=[0])]
+    p.leaf_mm = oracle.leaf_meta_from_bricks(p.V, src.levels, np.zeros_like(p.leaf_mm), l0)
+    for c in range(4):
+        p.gpu.set_metadata(c, p.leaf_mm[c])
+    ids = p.gpu.all_ids()
+    np.random.default_rng(8).shuffle(ids)
+    p.upload(0, ids[:170])
+    p.check_masks()
+    chans = []
+    for c, (lo, hi) in enumerate([(0, 4), (1, 4), (0, 3), (2, 4)]):
+        tf = synth.tf_hue(c / 4.0, 0.1)
+        if c % 2 == 0:
+            tf[:9] = tf[8]
+            tf[:9, 3] = 0.1  # haze: flat over the first nine entries
+        chans.append(dict(c=c, lo=lo, hi=hi, W0=100 * 256, W1=2000 * 256, tf=tf))
+    cam = synth.camera_persp((380.0, -120.0, 420.0), (128, 128, 128), (0, 0, 1), 45.0, 1.0)
+    st = torch.zeros(8, dtype=torch.int64, device="cuda")
+    res = p.frame(1, cam, 112, 112, 0.5, chans, lod_bias=1.5, stats=st, flags=resoct.RENDER_HOMOGENEOUS)
+    p.check_frame(res, "homog-cells")
+    st0 = torch.zeros(8, dtype=torch.int64, device="cuda")
+    p.gpu.render(2, cam, 112, 112, 0.5, chans, lod_bias=1.5, stats=st0)
+    torch.cuda.synchronize()
+    p.gpu.cache.read_requests(1 << 20)
+    st, st0 = st.cpu().numpy(), st0.cpu().numpy()
+    assert st[1] < st0[1]  # fewer brick reads
