@@ -437,6 +437,84 @@ def adaptive_bench(scene, fl, frames, reps=3):
     return out
 
 
+def homogeneous_bench(frames=(0, 12), reps=7, W=1920, H=1080, haze=0.05):
+    """Homogeneous leaves (RO_RENDER_HOMOGENEOUS) on a fully resident
+    4-channel 1024x1024x64 u16 cell volume whose leaf metadata are computed
+    on the GPU from the level-0 bricks (exact, so background leaves can be
+    homogeneous).  Channels 0 and 2 show a faint haze over the low values (a
+    table flat over its first nine entries), 1 and 3 are zero there.  Each
+    orbit frame is rendered plain and with the option, once untimed and then
+    `reps` times: median kernel time from HIP events, samples, brick reads,
+    distinct bricks read, and the largest image difference (zero where level
+    0 is read; homogeneous leaves read at coarse levels may differ from their
+    voxels' interpolation)."""
+    import torch
+    import synth
+    from paper_2309_04393_amd import resoct
+    from paper_2309_04393_amd.pipeline import GpuScene
+    vol = synth.CellVolume((1024, 1024, 64), 4, spacing=(1, 1, 4), n_levels=6, seed=2)
+    t = time.perf_counter()
+    n_all = resoct.Volume(vol.dims, vol.spacing, 4, 2, 32, vol.n_levels).brick_count()
+    scene = GpuScene(vol, 32, (16, 16, 4), 6, n_all, max_batch=4096, set_metadata=False)
+    unknown = np.zeros((scene.tree.n_leaves, 2), np.uint16)
+    unknown[:, 1] = 65535
+    for c in range(4):
+        scene.set_metadata(c, unknown)
+    ids = scene.all_ids()
+    scene.upload(0, ids)
+    scene.tree.update_residency()
+    torch.cuda.synchronize()
+    log(f"homogeneous leaves: {len(ids)} bricks resident ({time.perf_counter() - t:.1f} s)")
+    l0 = scene.all_ids(levels=[0])
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    scene.tree.leaf_metadata_from_bricks(l0)
+    b.record()
+    torch.cuda.synchronize()
+    out = {"workload": "4ch-1024x1024x64-u16, every brick resident, leaf metadata from the level-0 bricks",
+           "image": [W, H], "metadata_from_bricks_ms": a.elapsed_time(b), "level0_bricks": len(l0)}
+    chans = []
+    for c in range(4):
+        tf = synth.tf_hue(c / 4.0, 0.1)
+        if c % 2 == 0:
+            tf[:9] = tf[8]
+            tf[:9, 3] = haze
+        chans.append(dict(c=c, lo=0, hi=vol.n_levels - 1, W0=100 * 256, W1=2000 * 256, tf=tf))
+    cams = synth.orbit_path(vol.dims, vol.spacing, 24)
+    for cam in cams:
+        if cam["proj"] == "persp":
+            cam["tx"] = cam["ty"] * W / H
+    tf_dev = scene.tf_tensor(chans)
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    img = [torch.empty(W * H * 4, dtype=torch.float32, device="cuda") for _ in range(2)]
+    fno = 1
+    for f in frames:
+        row = {}
+        for k, (name, flags) in enumerate((("plain", 0), ("homogeneous", resoct.RENDER_HOMOGENEOUS))):
+            ms = []
+            for it in range(reps + 1):
+                stats.zero_()
+                fno += 1
+                a.record()
+                scene.render(fno, cams[f], W, H, 0.5, chans, tf_dev=tf_dev, out=img[k], stats=stats, flags=flags)
+                b.record()
+                torch.cuda.synchronize()
+                if it:  # the first render of each mode is untimed
+                    ms.append(a.elapsed_time(b))
+            st = stats.cpu().numpy()
+            _, nused = scene.cache.read_usage(fno)
+            scene.cache.read_requests(1 << 22)
+            row[name] = dict(ms=float(np.median(ms)), samples=int(st[0]), brick_reads=int(st[1]),
+                             bricks_read=int(nused), leaf_visits=int(st[3]))
+        row["speedup"] = row["plain"]["ms"] / row["homogeneous"]["ms"]
+        row["image_max_abs_diff"] = float((img[0] - img[1]).abs().max().item())
+        out[str(f)] = row
+        log(f"homogeneous leaves, frame {f}: {row}")
+    del scene
+    torch.cuda.empty_cache()
+    return out
+
+
 def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True, max_batch=64):
     """Serving on the 16-channel 2048 x 2048 x 64 cell volume, every brick
     resident in a 24 GiB cache: 64 clients, Poisson arrivals at `rate`
@@ -625,6 +703,8 @@ def main():
     ap.add_argument("--adaptive-frames", default="0,20",
                     help="fly-through frames of the adaptive-step measurement (each is made resident first; "
                          "the coarse bricks of zoomed-out frames take the host generator a while)")
+    ap.add_argument("--no-homogeneous", action="store_true",
+                    help="skip the homogeneous-leaves measurement (its own 4-channel scene)")
     ap.add_argument("--prefetch-only", action="store_true",
                     help="only the learned-prefetcher evaluation (10 training, 5 held-out paths)")
     ap.add_argument("--pf-lr", type=float, default=3e-3)
@@ -787,9 +867,12 @@ def main():
     if not args.no_adaptive:
         log("LOD-adaptive step on zoomed-out frames")
         out["adaptive_step"] = adaptive_bench(scene, fl, tuple(int(x) for x in args.adaptive_frames.split(",")))
-    if args.serve > 0 or not args.no_prefetch:
+    if args.serve > 0 or not args.no_prefetch or not args.no_homogeneous:
         del fl, store, scene
         torch.cuda.empty_cache()
+    if not args.no_homogeneous:
+        log("homogeneous leaves")
+        out["homogeneous_leaves"] = homogeneous_bench()
     if args.serve > 0:
         out["serving"] = serve_bench(args.rate, args.serve, max_batch=args.serve_max_batch)
     if not args.no_prefetch:

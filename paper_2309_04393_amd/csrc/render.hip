@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
     __shared__ uint32_t s_runs[NV * kMaxRuns];
     __shared__ LevLds s_lv[kMaxL];
     __shared__ NodeLds s_nd[kMaxD + 1];
-    __shared__ uint32_t s_flat[HOMOG ? NV * kMaxFlat : 1];  // runs of identical table entries
+    __shared__ uint32_t s_flat[HOMOG ? NV * (kMaxFlat + 1) : 1];  // runs of identical table entries
 
     stage_frame<NV>(A, s_tf, s_ch, s_runs, s_lv, s_nd, HOMOG ? s_flat : nullptr);
 

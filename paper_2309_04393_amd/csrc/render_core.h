@@ -48,7 +48,7 @@ struct RenderArgs {
 };
 
 struct ChanLds {
-    int c, lo, hi, nruns, nflat;
+    int c, lo, hi, nruns;
     float w0, iw;
     uint32_t ehi;     // one zero-opacity run starting at raw value 0: its last raw value, else ~0
     uint32_t single;  // same in every entry: every visible channel has such a run
@@ -595,7 +595,8 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                         while (cand) {
                             const int j = __builtin_ctz(cand);
                             cand &= cand - 1u;
-                            if (range_flat(nm[s_ch[j].c], s_flat + j * kMaxFlat, s_ch[j].nflat)) hm |= 1u << j;
+                            const uint32_t *fl = s_flat + j * (kMaxFlat + 1);
+                            if (range_flat(nm[s_ch[j].c], fl + 1, (int)fl[0])) hm |= 1u << j;
                         }
                     }
                     if (dl == D) {
@@ -776,7 +777,8 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 #pragma unroll
             for (int jj = 0; jj < kGroup; ++jj) {
                 const int j = g + jj;
-                ok[jj] = j < nvis && slot[j] != kInvalid && !(homog && ((hmask >> j) & 1u));
+                if constexpr (HOMOG) ok[jj] = j < nvis && slot[j] != kInvalid && !(homog && ((hmask >> j) & 1u));
+                else ok[jj] = j < nvis && slot[j] != kInvalid;
                 const int lu = (int)((lvpack >> (4 * j)) & 15u);
                 if (ok[jj] && lu != lprev) {
                     const LevLds lv = s_lv[lu];
@@ -812,12 +814,33 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 #pragma unroll
             for (int jj = 0; jj < kGroup; ++jj) {
                 const int j = g + jj;
-                // a homogeneous channel takes the leaf's minimum (every value
-                // of the leaf's range maps to the same table result)
-                const bool hv = homog && j < nvis && ((hmask >> j) & 1u);
-                if (!ok[jj] && !hv) continue;
                 float v;
-                if (ok[jj]) {
+                if constexpr (HOMOG) {
+                    // a homogeneous channel takes the leaf's minimum (every
+                    // value of the leaf's range maps to the same table result)
+                    const bool hv = homog && j < nvis && ((hmask >> j) & 1u);
+                    if (!ok[jj] && !hv) continue;
+                    if (ok[jj]) {
+                        const float f0 = fq[jj][0], f1 = fq[jj][1], f2 = fq[jj][2];
+                        float v00[2], v10[2], v01[2], v11[2];
+                        unpack<BPV>(w[jj][0], v00);
+                        unpack<BPV>(w[jj][1], v10);
+                        unpack<BPV>(w[jj][2], v01);
+                        unpack<BPV>(w[jj][3], v11);
+                        const float c00 = v00[0] + (v00[1] - v00[0]) * f0;
+                        const float c10 = v10[0] + (v10[1] - v10[0]) * f0;
+                        const float c01 = v01[0] + (v01[1] - v01[0]) * f0;
+                        const float c11 = v11[0] + (v11[1] - v11[0]) * f0;
+                        const float e0 = c00 + (c10 - c00) * f1;
+                        const float e1 = c01 + (c11 - c01) * f1;
+                        v = e0 + (e1 - e0) * f2;
+                        ++st_reads;
+                        if (AOV) A.aov[((size_t)py * A.W + px) * L + (int)((lvpack >> (4 * j)) & 15u)] += 1;
+                    } else {
+                        v = (float)(A.meta[(size_t)cur_leaf * m + s_ch[j].c] & 0xFFFFu);
+                    }
+                } else {
+                    if (!ok[jj]) continue;
                     const float f0 = fq[jj][0], f1 = fq[jj][1], f2 = fq[jj][2];
                     float v00[2], v10[2], v01[2], v11[2];
                     unpack<BPV>(w[jj][0], v00);
@@ -831,10 +854,6 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     const float e0 = c00 + (c10 - c00) * f1;
                     const float e1 = c01 + (c11 - c01) * f1;
                     v = e0 + (e1 - e0) * f2;
-                    ++st_reads;
-                    if (AOV) A.aov[((size_t)py * A.W + px) * L + (int)((lvpack >> (4 * j)) & 15u)] += 1;
-                } else {
-                    v = (float)(A.meta[(size_t)cur_leaf * m + s_ch[j].c] & 0xFFFFu);
                 }
                 const ChanLds ch = s_ch[j];
                 float x = (v - ch.w0) * ch.iw;
@@ -849,11 +868,15 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 const float r = ta.x + (tb.x - ta.x) * f;
                 const float gg = ta.y + (tb.y - ta.y) * f;
                 const float bb = ta.z + (tb.z - ta.z) * f;
+                if constexpr (!HOMOG) ++st_reads;
                 prod *= 1.0f - al;
                 sa += al;
                 sr += al * r;
                 sg += al * gg;
                 sbl += al * bb;
+                if constexpr (!HOMOG) {
+                    if (AOV) A.aov[((size_t)py * A.W + px) * L + (int)((lvpack >> (4 * j)) & 15u)] += 1;
+                }
             }
             // the next group's loads are issued after this group is used:
             // bounds the registers held by loads in flight
@@ -932,10 +955,13 @@ __device__ __forceinline__ void stage_frame(const RenderArgs &A, float4 *s_tf, C
         const uint32_t r0 = s_runs[t * kMaxRuns];
         ch.ehi = (ch.nruns == 1 && (r0 & 0xFFFFu) == 0) ? (r0 >> 16) : 0xFFFFFFFFu;
         ch.single = 0;
-        ch.nflat = 0;
         s_ch[t] = ch;
-        if (s_flat && (A.flags & RO_RENDER_HOMOGENEOUS))
-            s_ch[t].nflat = build_flat_runs(s_tf + t * 256, A.W0[t], A.W1[t], s_flat + t * kMaxFlat);
+        if (s_flat) {
+            // word 0 of the channel's block: the run count; the runs follow
+            uint32_t *fl = s_flat + t * (kMaxFlat + 1);
+            fl[0] = (A.flags & RO_RENDER_HOMOGENEOUS) ? (uint32_t)build_flat_runs(s_tf + t * 256, A.W0[t], A.W1[t], fl + 1)
+                                                      : 0u;
+        }
     }
     __syncthreads();
     if (t < (unsigned)nvis) {
