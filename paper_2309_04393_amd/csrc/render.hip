@@ -102,13 +102,21 @@ static hipError_t launch_one(const RenderArgs &A, const QueueLaunch &Q, hipStrea
 }
 
 // Compile-time brick edges: 32^3 and 16^3 bricks with their halo (the AOV
-// diagnostic output, the LOD-adaptive step and homogeneous leaves take the
-// generic kernel; homogeneous leaves and AOV in an instantiation of their own).
+// diagnostic output and the LOD-adaptive step take the generic kernel).
+// Homogeneous leaves have instantiations of their own, so the kernels that
+// do not take them carry none of their code.
 template <int NV, int BPV>
 static hipError_t launch_nv(const RenderArgs &A, bool aov, const QueueLaunch &Q, hipStream_t s) {
     if (aov) return launch_one<NV, BPV, true, 0, true>(A, Q, s);
-    if (A.flags & RO_RENDER_HOMOGENEOUS) return launch_one<NV, BPV, false, 0, true>(A, Q, s);
-    if (A.flags & RO_RENDER_ADAPTIVE_STEP) return launch_one<NV, BPV, false, 0>(A, Q, s);
+    if (A.flags & RO_RENDER_ADAPTIVE_STEP) {
+        if (A.flags & RO_RENDER_HOMOGENEOUS) return launch_one<NV, BPV, false, 0, true>(A, Q, s);
+        return launch_one<NV, BPV, false, 0>(A, Q, s);
+    }
+    if (A.flags & RO_RENDER_HOMOGENEOUS) {
+        if (A.E == 34) return launch_one<NV, BPV, false, 34, true>(A, Q, s);
+        if (A.E == 18) return launch_one<NV, BPV, false, 18, true>(A, Q, s);
+        return launch_one<NV, BPV, false, 0, true>(A, Q, s);
+    }
     if (A.E == 34) return launch_one<NV, BPV, false, 34>(A, Q, s);
     if (A.E == 18) return launch_one<NV, BPV, false, 18>(A, Q, s);
     return launch_one<NV, BPV, false, 0>(A, Q, s);

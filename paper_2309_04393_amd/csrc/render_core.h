@@ -108,6 +108,7 @@ __device__ __forceinline__ bool range_empty(uint32_t mm, const uint32_t *runs, i
 // entries at either end can hold such a range (a strictly increasing table
 // position is constant only where it is clamped), so at most 129 are kept.
 constexpr int kMaxFlat = 130;
+constexpr uint32_t kHomTag = 0x80000000u;  // slot word of a homogeneous channel: tag | leaf minimum (slots < 2^31)
 __device__ inline int build_flat_runs(const float4 *tf, uint32_t W0, uint32_t W1, uint32_t *runs) {
     int n = 0, e = 0;
     const uint64_t den = (uint64_t)W1 - (uint64_t)W0;
@@ -346,7 +347,9 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     uint32_t cur_leaf = kInvalid;
     int cur_lod = -1, lod = 0;
     uint32_t emask = 0, missmask = 0;
-    uint32_t hmask = 0;  // channels homogeneous in the current leaf: sampled from its metadata
+    // channels homogeneous in the current leaf (set at each visit, not kept
+    // across samples): their slot word holds kHomTag | the leaf minimum
+    uint32_t hmask = 0;
     uint64_t lvpack = 0;
     uint32_t nvisit = 0;
     int lc[3] = {-1, -1, -1};  // L0 origin of the last visited leaf (none yet)
@@ -627,6 +630,31 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 cur_leaf = leaf;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) lc[a] = (iu[a] >> field(leafl.nsh, a)) << field(leafl.nsh, a);
+                if constexpr (HOMOG) {
+                    if (homog) {
+                        // the new leaf's homogeneous channels carry its minimum
+                        // in their slot word (the lookups below keep such words);
+                        // tags of the previous leaf go
+                        for (int j = 0; j < nvis; ++j) {
+                            const uint32_t sw = slot[j];
+                            if ((hmask >> j) & 1u)
+                                slot[j] = kHomTag | (A.meta[(size_t)leaf * m + s_ch[j].c] & 0xFFFFu);
+                            else if (sw != kInvalid && (sw & kHomTag))
+                                slot[j] = kInvalid;
+                        }
+                    }
+                }
+            } else {
+                if constexpr (HOMOG) {
+                    if (homog) {
+                        // same leaf, new level: the homogeneous channels are the tagged slot words
+                        hmask = 0;
+                        for (int j = 0; j < nvis; ++j) {
+                            const uint32_t sw = slot[j];
+                            if (sw != kInvalid && (sw & kHomTag)) hmask |= 1u << j;
+                        }
+                    }
+                }
             }
             cur_lod = lod;
             ++st_visits;
@@ -723,6 +751,14 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     for (int jj = 0; jj < kGroup; ++jj) {
                         const int j = g + jj;
                         ns[jj] = kInvalid;
+                        if constexpr (HOMOG) {
+                            // a homogeneous channel keeps a tagged word (a real
+                            // slot of an earlier leaf is dropped)
+                            if (j < nvis && ((hmask >> j) & 1u)) {
+                                const uint32_t sw = slot[j];
+                                if (sw != kInvalid && (sw & kHomTag)) ns[jj] = sw;
+                            }
+                        }
                         if ((look >> j) & 1u) {
                             if ((reuse >> j) & 1u) {
                                 ns[jj] = slot[j];
@@ -739,7 +775,10 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     for (int jj = 0; jj < kGroup; ++jj) {
                         const int j = g + jj;
                         if (j >= nvis) break;
-                        if (ns[jj] == kInvalid) {
+                        bool no_slot;
+                        if constexpr (HOMOG) no_slot = ns[jj] >= kHomTag;  // none, or a tagged word
+                        else no_slot = ns[jj] == kInvalid;
+                        if (no_slot) {
                             lvpack &= ~((uint64_t)15u << (4 * j));
                         } else {
                             nhave |= 1u << j;
@@ -777,7 +816,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 #pragma unroll
             for (int jj = 0; jj < kGroup; ++jj) {
                 const int j = g + jj;
-                if constexpr (HOMOG) ok[jj] = j < nvis && slot[j] != kInvalid && !(homog && ((hmask >> j) & 1u));
+                if constexpr (HOMOG) ok[jj] = j < nvis && slot[j] < kHomTag;
                 else ok[jj] = j < nvis && slot[j] != kInvalid;
                 const int lu = (int)((lvpack >> (4 * j)) & 15u);
                 if (ok[jj] && lu != lprev) {
@@ -818,8 +857,12 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 if constexpr (HOMOG) {
                     // a homogeneous channel takes the leaf's minimum (every
                     // value of the leaf's range maps to the same table result)
-                    const bool hv = homog && j < nvis && ((hmask >> j) & 1u);
-                    if (!ok[jj] && !hv) continue;
+                    uint32_t sw = kInvalid;
+                    if (!ok[jj]) {
+                        if (!homog || j >= nvis) continue;
+                        sw = slot[j];
+                        if (sw == kInvalid || !(sw & kHomTag)) continue;
+                    }
                     if (ok[jj]) {
                         const float f0 = fq[jj][0], f1 = fq[jj][1], f2 = fq[jj][2];
                         float v00[2], v10[2], v01[2], v11[2];
@@ -837,7 +880,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                         ++st_reads;
                         if (AOV) A.aov[((size_t)py * A.W + px) * L + (int)((lvpack >> (4 * j)) & 15u)] += 1;
                     } else {
-                        v = (float)(A.meta[(size_t)cur_leaf * m + s_ch[j].c] & 0xFFFFu);
+                        v = (float)(sw & 0xFFFFu);
                     }
                 } else {
                     if (!ok[jj]) continue;
