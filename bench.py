@@ -828,6 +828,10 @@ def main():
         "channel_samples_per_s": ch_samples / (t1 - t0),
         "render_samples_per_s": samples / (np.sum(render_ms) / 1000.0),
         "uploads_per_frame": float(np.mean([len(p) for p in plans])),
+        # bricks the frames read (every sample at its desired level, nothing missing in steady
+        # state): the GPU memory the method needs per frame under these viewing conditions
+        "bricks_read_per_frame": float(np.mean(usage)),
+        "memory_read_per_frame_GB": float(np.mean(usage)) * scene.cache.slot_stride / 1e9,
         "lane_busy": float(st[0]) / max(float(st[5]), 1.0),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(cfg["name"]),
