@@ -390,3 +390,22 @@ def test_homogeneous_leaves_cells_channels():
     p.gpu.cache.read_requests(1 << 20)
     st, st0 = st.cpu().numpy(), st0.cpu().numpy()
     assert st[1] < st0[1]  # fewer brick reads
+
+
+@pytest.mark.parametrize("adaptive", [False, True])
+def test_homogeneous_leaves_with_aov_and_adaptive_step(cfg1, adaptive):
+    """The homogeneous option in the AOV kernel and together with the
+    LOD-adaptive step (the generic-edge instantiation): levels 0..2, about
+    60 % resident; images, requests, usage and per-level sample counts (which
+    leave homogeneous samples out) against the oracle."""
+    p = Pair(cfg1, 16, (8, 8, 8), 3, n_slots=73)
+    ids = p.gpu.all_ids()
+    p.upload(0, ids[np.random.default_rng(11).random(len(ids)) < 0.6])
+    p.check_masks()
+    cam = synth.camera_persp((120.0, 95.0, 80.0), (32, 30, 34), (0, 0, 1), 50.0, 1.25)
+    flags = resoct.RENDER_HOMOGENEOUS | (resoct.RENDER_ADAPTIVE_STEP if adaptive else 0)
+    res = p.frame(1, cam, 100, 80, 0.5, _plateau_chans(0, 2), lod_bias=3.0 if adaptive else 0.8, aov=True,
+                  flags=flags)
+    p.check_frame(res, f"homog-aov-{adaptive}")
+    amb = res["o"]["amb_pix"] == 0
+    assert np.array_equal(res["aov"][amb], res["o"]["aov"][amb])
