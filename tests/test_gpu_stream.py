@@ -301,3 +301,30 @@ def test_channel_exchange():
     g.tree.update_residency()
     assert np.array_equal(g.tree.masks(), oracle.masks(V, sim.res_slot))
     frame(4, "exchange-after")
+
+
+def test_leaf_metadata_from_u8_bricks():
+    """The u8 path of the metadata-from-bricks kernel: from every level-0
+    brick of the 64^3 blob volume the derived metadata equal the oracle's and
+    the data server's exact leaf metadata (L0 values within one voxel of the
+    leaf); then level-1 bricks alone give the oracle's coarse estimate."""
+    src = synth.config1_volume()
+    p = Pair(src, 16, (8, 8, 8), 3, n_slots=73)
+    n_leaves = p.leaf_mm.shape[1]
+    unknown = np.zeros((1, n_leaves, 2), np.uint16)
+    unknown[..., 1] = 255
+    p.gpu.set_metadata(0, unknown[0])
+    ids = p.gpu.all_ids()
+    p.upload(0, ids)
+    l0 = [int(i) for i in p.gpu.all_ids(levels=[0])]
+    p.gpu.tree.leaf_metadata_from_bricks(np.array(l0, np.uint32))
+    torch.cuda.synchronize()
+    ref = oracle.leaf_meta_from_bricks(p.V, src.levels, unknown, l0)
+    assert np.array_equal(ref, p.leaf_mm)  # the server's exact metadata
+    assert np.array_equal(p.gpu.tree.meta(), oracle.meta_all(p.V, ref))
+    p.gpu.set_metadata(0, unknown[0])
+    l1 = [int(i) for i in p.gpu.all_ids(levels=[1])]
+    p.gpu.tree.leaf_metadata_from_bricks(np.array(l1, np.uint32))
+    torch.cuda.synchronize()
+    ref1 = oracle.leaf_meta_from_bricks(p.V, src.levels, unknown, l1)
+    assert np.array_equal(p.gpu.tree.meta(), oracle.meta_all(p.V, ref1))
