@@ -658,3 +658,148 @@ def test_cell_metadata_is_conservative():
             x, y, z = li % 16, (li // 16) % 16, li // 256
             blk = pad[z * 4:z * 4 + 6, y * 16:y * 16 + 18, x * 16:x * 16 + 18]
             assert blk.max() <= lm[c, li]
+
+
+# ------------------------------------------------------- desired level rule
+#
+# Alg. 1 chooseResolutionLevel with the reading of Sec. 6.2 (the level can be
+# any function of the distance): level l (l >= 1) is desired from the distance
+# on where a pixel's footprint beta * t * (2 ty / H) reaches the level's x voxel
+# size.  The volume below has anisotropic spacing (1, 3, 1), so the x and y
+# voxel sizes of each level differ (x: 1, 2, 4, ..., y: 3, 3, 6, ...), and
+# non-square pixels (tx / W != ty / H); each level array holds its own
+# constant, so the level a sample reads shows in the opacity as well as in
+# the per-level sample counts.
+
+_LVL_VALUE = [1, 2, 3, 4, 5, 6]  # raw u8 value held by every voxel of level l
+
+
+def _level_constant_scene():
+    V = oracle.make_volume((64, 8, 8), (1, 3, 1), 1, 8, 16, 6, (4, 4, 4), 4)
+    d, _, _ = oracle.level_info(V)
+    levels = [[np.full((d[l][2], d[l][1], d[l][0]), _LVL_VALUE[l], np.uint8) for l in range(6)]]
+    ch = [dict(c=0, lo=0, hi=5, W0=0, W1=255 * 256, tf=synth.tf_ramp())]
+    return V, levels, ch
+
+
+def _expected_alpha(level_seq):
+    """1 - prod(1 - alpha_k) with alpha_k the ramp table's entry at the raw
+    value of the level sample k reads (window [0, 255]: entry v exactly)."""
+    tf = synth.tf_ramp()
+    T = 1.0
+    for l in level_seq:
+        T *= 1.0 - float(tf[_LVL_VALUE[l], 3])
+    return 1.0 - T
+
+
+def test_desired_level_perspective_thresholds():
+    """A perspective ray along +x from an eye 3.7 units before the volume,
+    step 0.5, beta = 2, 2 ty / H = 2 * 0.1875 / 3 = 0.125: the footprint is
+    0.25 t, so level l is desired from t = 4 * 2^l on (t = 8, 16, 32, 64 for
+    levels 1-4; samples k = 16, 32, 64, 128 lie exactly on them).  The samples
+    inside the box are k = 8 (x = 0.3) .. 135 (x = 63.8); by hand they read
+    8 x L0, 16 x L1, 32 x L2, 64 x L3, 8 x L4."""
+    V, levels, ch = _level_constant_scene()
+    cam = dict(proj="persp", eye=[-3.7, 4.3 * 3, 4.3], F=[1.0, 0.0, 0.0], R=[0.0, 0.0, 1.0],
+               U=[0.0, 1.0, 0.0], tx=0.2, ty=0.1875)
+    fr, keep = oracle.make_frame(cam, 1, 3, 0.5, ch, term_alpha=1.0, lod_bias=2.0)
+    res = np.arange(oracle.brick_count(V), dtype=np.int32)
+    lm = _leaf_mm_full(V, levels)
+    r = oracle.render(V, levels, res, lm, fr, oracle.brick_count(V), aov=True)
+    # pixel row 1 of 3 is the axis ray (b = 0)
+    expect = [8, 16, 32, 64, 8, 0]
+    assert r["aov"][1, 0].tolist() == expect
+    seq = [0] * 8 + [1] * 16 + [2] * 32 + [3] * 64 + [4] * 8
+    assert abs(r["rgba"][1, 0, 3] - _expected_alpha(seq)) < 1e-12
+
+
+@pytest.mark.parametrize("beta,level", [
+    (0.5, 0),      # footprint 1.5 < 2
+    (1.0, 1),      # 3: >= 2, < 4
+    (4.0 / 3, 2),  # 4: exactly the level-2 x voxel size (>=); y sizes would give 1
+    (2.0, 2),      # 6: >= 4, < 8
+    (16.0 / 3, 4), # 16: exactly level 4
+])
+def test_desired_level_orthographic(beta, level):
+    """Orthographic views use the constant pixel size 2 ty / H = 3 (ty = 1.5,
+    H = 1; the horizontal size 2 tx / W = 1/3 differs): level l is desired
+    iff beta * 3 >= the level's x voxel size 2^l.  Every pixel reads the
+    same level at its single sample."""
+    V, levels, ch = _level_constant_scene()
+    cam = dict(proj="ortho", eye=[31.3, 4.3 * 3, 4.3 - 1000.0], F=[0.0, 0.0, 1.0], R=[1.0, 0.0, 0.0],
+               U=[0.0, 1.0, 0.0], tx=0.5, ty=1.5)
+    fr, keep = oracle.make_frame(cam, 3, 1, 1000.0, ch, term_alpha=1.0, lod_bias=beta)
+    res = np.arange(oracle.brick_count(V), dtype=np.int32)
+    r = oracle.render(V, levels, res, _leaf_mm_full(V, levels), fr, oracle.brick_count(V), aov=True)
+    for i in range(3):
+        want = [0] * 6
+        want[level] = 1
+        assert r["aov"][0, i].tolist() == want, (beta, i, r["aov"][0, i])
+        assert abs(r["rgba"][0, i, 3] - _expected_alpha([level])) < 1e-12
+
+
+def test_desired_level_clamped_per_channel():
+    """Sec. 6.2: the distance rule's level is clamped to each channel's range.
+    Two visible copies of the level-constant volume on the perspective ray
+    above, one limited to levels [1, 2] and one to [3, 5]: per-level counts
+    are the hand-computed ones with the clamp applied."""
+    V1, levels, _ = _level_constant_scene()
+    V = oracle.make_volume((64, 8, 8), (1, 3, 1), 2, 8, 16, 6, (4, 4, 4), 4)
+    lv = [levels[0], levels[0]]
+    ch = [dict(c=0, lo=1, hi=2, W0=0, W1=255 * 256, tf=synth.tf_ramp()),
+          dict(c=1, lo=3, hi=5, W0=0, W1=255 * 256, tf=synth.tf_ramp())]
+    cam = dict(proj="persp", eye=[-3.7, 4.3 * 3, 4.3], F=[1.0, 0.0, 0.0], R=[0.0, 0.0, 1.0],
+               U=[0.0, 1.0, 0.0], tx=0.2, ty=0.1875)
+    fr, keep = oracle.make_frame(cam, 1, 3, 0.5, ch, term_alpha=1.0, lod_bias=2.0)
+    res = np.arange(oracle.brick_count(V), dtype=np.int32)
+    r = oracle.render(V, lv, res, _leaf_mm_full(V, lv), fr, oracle.brick_count(V), aov=True)
+    seq = [0] * 8 + [1] * 16 + [2] * 32 + [3] * 64 + [4] * 8
+    a = [min(max(l, 1), 2) for l in seq]
+    b = [min(max(l, 3), 5) for l in seq]
+    assert r["aov"][1, 0].tolist() == [sum(1 for x in a + b if x == l) for l in range(6)]
+    # the two channels mix per sample: 1 - prod over samples and channels
+    assert abs(r["rgba"][1, 0, 3] - _expected_alpha(a + b)) < 1e-12
+
+
+def test_paper_scale_metadata_is_conservative():
+    """Leaf metadata of the 16-channel 8192 x 8192 x 192 tissue volume (cell
+    maxima times the tissue mask and the per-channel gain) bound every L0
+    voxel within one voxel of the leaf (the trilinear footprint), checked on
+    more than 10^6 voxels per channel: 340 random leaves of the volume and,
+    per channel, 50 leaves with maximum 0 next to a non-empty leaf (where a
+    bound that misses the mask's edge or a cell reaching over the leaf face
+    would show)."""
+    cv = synth.config3_volume()
+    leaf, grid = (16, 16, 8), (512, 512, 32)
+    lm = cv.leaf_max_all(leaf, grid)  # [16][n_leaves]
+    lmg = lm.reshape(16, grid[2], grid[1], grid[0])
+    rng = np.random.default_rng(30)
+    nz = 192 // leaf[2]
+    picks = [(int(x), int(y), int(z)) for x, y, z in
+             zip(rng.integers(0, 512, 340), rng.integers(0, 512, 340), rng.integers(0, nz, 340))]
+    # empty leaves bordering a non-empty one in x or y (any channel)
+    occ = (lmg[:, :nz] > 0)
+    border = np.zeros_like(occ)
+    border[:, :, :, 1:] |= occ[:, :, :, :-1]
+    border[:, :, :, :-1] |= occ[:, :, :, 1:]
+    border[:, :, 1:, :] |= occ[:, :, :-1, :]
+    border[:, :, :-1, :] |= occ[:, :, 1:, :]
+    border &= ~occ
+    for c in range(16):
+        zz, yy, xx = np.nonzero(border[c])
+        sel = rng.choice(len(zz), 50, replace=False)
+        picks += [(int(xx[i]), int(yy[i]), int(zz[i])) for i in sel]
+    checked = np.zeros(16, np.int64)
+    n_empty_checked = 0
+    for (x, y, z) in picks:
+        lo = [max(0, x * leaf[0] - 1), max(0, y * leaf[1] - 1), max(0, z * leaf[2] - 1)]
+        hi = [min(8192, (x + 1) * leaf[0] + 1), min(8192, (y + 1) * leaf[1] + 1),
+              min(192, (z + 1) * leaf[2] + 1)]
+        reg = cv.region(0, lo[0], lo[1], lo[2], hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2])
+        li = (z * grid[1] + y) * grid[0] + x
+        vmax = reg.reshape(16, -1).max(axis=1)
+        bound = lm[:, li]
+        assert (vmax <= bound).all(), ((x, y, z), vmax.tolist(), bound.tolist())
+        checked += reg[0].size
+        n_empty_checked += int((bound == 0).sum())
+    assert checked.min() >= 10 ** 6 and n_empty_checked >= 16 * 50
