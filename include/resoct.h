@@ -26,7 +26,7 @@
  *    calls, pointers are handed over at create time, and the library never
  *    frees them.  Destroy calls free host handle memory only.  Device buffers
  *    must be 256-byte aligned.
- *  - Brick IDs (Sec. 6): 32-bit, page-table ID c*k + l in bits 24-31 (c =
+ *  - Brick IDs (Sec. 7): 32-bit, page-table ID c*k + l in bits 24-31 (c =
  *    cache channel, l = level, k = number of levels), brick z in bits 16-23,
  *    y in 8-15, x in 0-7.  Hence at most 256 bricks per axis per level and
  *    m*k <= 256 page tables.
@@ -79,7 +79,7 @@ typedef struct {
 } ro_volume_desc;
 
 /* Validates and derives the level schedule.  RO_E_CAPACITY when a level has
- * more than 256 bricks on an axis or m*k > 256 (brick-ID capacity, Sec. 6). */
+ * more than 256 bricks on an axis or m*k > 256 (brick-ID capacity, Sec. 7). */
 ro_status ro_volume_create(const ro_volume_desc *desc, ro_volume **out);
 void ro_volume_destroy(ro_volume *v);
 
@@ -91,7 +91,7 @@ ro_status ro_volume_levels(const ro_volume *v, int32_t *dims_out, int32_t *facto
 /* Total bricks over all channels and levels (= page-table entries). */
 ro_status ro_volume_brick_count(const ro_volume *v, uint64_t *count);
 
-/* Brick ID encode / decode (Sec. 6).  RO_E_ARG for out-of-range fields. */
+/* Brick ID encode / decode (Sec. 7).  RO_E_ARG for out-of-range fields. */
 ro_status ro_brick_id_encode(const ro_volume *v, uint32_t c, uint32_t l, const uint32_t b[3],
                              uint32_t *id);
 ro_status ro_brick_id_decode(const ro_volume *v, uint32_t id, uint32_t *c, uint32_t *l,
@@ -340,7 +340,7 @@ typedef struct {
     uint32_t win_hi[RO_MAX_CHANNELS];
     const float *tf_dev;  /* device [n_vis][256][4] RGBA, alpha >= 0 */
     float term_alpha;     /* in (0, 1] */
-    int32_t start_level;  /* traversal start level (Sec. 6, implementation), -1: the octree's */
+    int32_t start_level;  /* traversal start level (Sec. 7, implementation), -1: the octree's */
     uint32_t flags;       /* RO_RENDER_*; other bits are rejected (RO_E_ARG) */
     uint32_t *aov_dev;    /* RO_RENDER_AOV: device [H][W][k] uint32, zeroed by the caller */
     unsigned long long *stats_dev; /* optional device [8], accumulated (not cleared): [0] ray

@@ -15,7 +15,7 @@
  *  - Brick hierarchy, bricks of equal voxel size, per-level extent:
  *    Sec. 3 "Brick hierarchy".
  *  - Partially mapped nodes: Sec. 3 "Fully vs. partially mapped".
- *  - Brick IDs: 24-bit spatial offset + 8-bit page-table ID: Sec. 6.
+ *  - Brick IDs: 24-bit spatial offset + 8-bit page-table ID: Sec. 7.
  *  - Residency masks (OR of children, leaves marked by overlapping bricks,
  *    eviction recheck): Sec. 5.3 "Updating residency information",
  *    "LRU cache eviction".
@@ -125,7 +125,7 @@ static inline long long dense(const geo_t *G, int c, int l, int bx, int by, int 
     return G->off[c][l] + ((long long)bz * G->nb[l][1] + by) * G->nb[l][0] + bx;
 }
 
-/* Brick ID (Sec. 6): 8-bit page-table ID in the top byte, then z, y, x
+/* Brick ID (Sec. 7): 8-bit page-table ID in the top byte, then z, y, x
  * offsets of 8 bits each; the page table of (channel c, level l) has ID
  * c * k + l where k is the number of levels. */
 uint32_t or_brick_id(int n_levels, int c, int l, int bx, int by, int bz) {

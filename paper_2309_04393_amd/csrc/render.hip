@@ -1,8 +1,8 @@
 // Ray-guided mixed-resolution multi-channel ray casting over the residency
-// octree (Sec. 6.1, Alg. 1; Sec. 6.2; Sec. 6 implementation notes).
+// octree (Sec. 6.1, Alg. 1; Sec. 6.2; Sec. 7 implementation notes).
 //
-// One lane per ray; persistent 1024-lane workgroups whose waves take
-// 8 x 8-pixel blocks from a queue.
+// One lane per ray; persistent 768-lane workgroups (one per CU) whose waves
+// take 8 x 8-pixel blocks from per-XCD queues.
 // Sample positions and every integer decision derived from them (box, leaf,
 // brick, level) are computed in FP64; interpolation, transfer functions and
 // the channel mix in FP32; the compositing state in FP64.  Per lane, the
@@ -22,10 +22,11 @@
 
 namespace ro {
 
-// Workgroups of kRenderLanes lanes (768: 3 waves per SIMD, up to 168 VGPRs,
-// no spills), one per CU: one copy of the frame's LDS tables plus the
-// per-lane slot words.  1024 lanes (4 waves per SIMD, 128 VGPRs) spill and
-// measured 1-10 % slower, 512 lanes 35 % slower.
+// Workgroups of kRenderLanes lanes (768: 3 waves per SIMD, up to 168 VGPRs),
+// one per CU: one copy of the frame's LDS tables plus the per-lane slot
+// words.  The 16-channel instantiations for 32^3 bricks keep 12 bytes per
+// lane in scratch (the others none).  1024 lanes (4 waves per SIMD, 128
+// VGPRs) spill more and measured 1-10 % slower, 512 lanes 35 % slower.
 
 // Lanes refill only when the whole wave is idle: a wave then takes a whole
 // new 8 x 8 block and its rays start together.  Refilling single lanes as

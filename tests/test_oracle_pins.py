@@ -2,7 +2,7 @@
 library routines, brute force on tiny inputs and the paper's invariants.
 
 Paper sections cited: Sec. 3 (partial / full mapping and their propagation),
-Sec. 5.3 (incremental residency update and LRU eviction), Sec. 6 (brick ID
+Sec. 5.3 (incremental residency update and LRU eviction), Sec. 7 (brick ID
 layout), Sec. 6.1 / Alg. 1 (per-sample traversal, requests, substitution),
 Sec. 6.2 (per-channel resolution ranges)."""
 from __future__ import annotations
@@ -36,7 +36,7 @@ def _read_golden(name):
 
 
 def test_brick_id_golden():
-    """Sec. 6: 24 bits of spatial offset (8 each for x, y, z) and 8 bits of
+    """Sec. 7: 24 bits of spatial offset (8 each for x, y, z) and 8 bits of
     page-table ID for (m x k) <= 256 page tables."""
     for row in _read_golden("brick_ids.txt"):
         k, c, l, bx, by, bz, expect = (int(x, 0) for x in row)
