@@ -161,6 +161,20 @@ ro_status ro_stream_bricks(ro_cache *c, uint32_t frame, uint32_t n, const uint32
 ro_status ro_read_requests(ro_cache *c, uint32_t cap, uint32_t *ids_host, uint32_t *counts_host,
                            uint32_t *n_unique, uint64_t *total_missing, void *stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same readback
+ * as ro_read_requests (same outputs, counters cleared the same way), with its
+ * work space in a fixed device array of the library instead of the cache's
+ * scratch buffer.  Allocates nothing.  Limits: cap <= RO_NOALLOC_MAX_PAIRS
+ * and a volume of at most 2^26 bricks; beyond them RO_E_CAPACITY and nothing
+ * is enqueued.  The array (about 2.5 MiB) exists once per GPU until the
+ * process ends and keeps the last call's contents; every call on a GPU uses
+ * that GPU's copy, so calls that overlap on one GPU (other threads or
+ * streams) race.  Synchronises. */
+#define RO_NOALLOC_MAX_PAIRS 262144u
+ro_status ro_read_requests_noalloc(ro_cache *c, uint32_t cap, uint32_t *ids_host, uint32_t *counts_host,
+                                   uint32_t *n_unique, uint64_t *total_missing, void *stream);
+
 /* Slots read during frame `frame` (stamp == frame), ascending, at most cap;
  * *n_out receives the full count.  Synchronises. */
 ro_status ro_read_usage(ro_cache *c, uint32_t frame, uint32_t cap, uint32_t *slots_host,

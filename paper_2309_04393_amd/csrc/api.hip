@@ -187,8 +187,7 @@ static CacheScratch cache_scratch_layout(const VolGeo &g, const ro_cache_desc &d
     s.uploads = take(sizeof(uint32_t) * d.max_batch);
     s.srcidx = take(sizeof(uint32_t) * d.max_batch);
     s.touch = take(sizeof(uint32_t) * d.max_batch);
-    s.nblk = (uint32_t)((g.total + 1023) / 1024);
-    s.blk = take(sizeof(uint32_t) * (s.nblk + 1) * 2 + 16);
+    s.compact = take(compact_scratch_bytes(g.total, (uint32_t)g.total));
     size_t n_slots_or_total = std::max<uint64_t>(g.total, d.n_slots);
     s.outpairs = take(sizeof(uint32_t) * 2 * n_slots_or_total);
     s.total = o;
@@ -400,6 +399,13 @@ extern "C" ro_status ro_read_requests(ro_cache *c, uint32_t cap, uint32_t *ids, 
     RO_CHECK(c && n_unique && total, RO_E_ARG, "null argument");
     RO_CHECK(cap == 0 || (ids && counts), RO_E_ARG, "null output arrays");
     return read_requests_device(c, cap, ids, counts, n_unique, total, (hipStream_t)stream);
+}
+
+extern "C" ro_status ro_read_requests_noalloc(ro_cache *c, uint32_t cap, uint32_t *ids, uint32_t *counts,
+                                              uint32_t *n_unique, uint64_t *total, void *stream) {
+    RO_CHECK(c && n_unique && total, RO_E_ARG, "null argument");
+    RO_CHECK(cap == 0 || (ids && counts), RO_E_ARG, "null output arrays");
+    return read_requests_noalloc_device(c, cap, ids, counts, n_unique, total, (hipStream_t)stream);
 }
 
 extern "C" ro_status ro_read_usage(ro_cache *c, uint32_t frame, uint32_t cap, uint32_t *slots,

@@ -105,10 +105,9 @@ struct CacheScratch {
     size_t uploads;    // max_batch uint32 dense indices
     size_t srcidx;     // max_batch uint32 staged index
     size_t touch;      // max_batch uint32 slots to touch
-    size_t blk;        // compaction block counts
-    size_t outpairs;   // compaction output (id, count) pairs, capacity = brick count
+    size_t compact;    // request compaction work space (compact_scratch_bytes of every brick)
+    size_t outpairs;   // usage readback output and LRU candidate slots
     size_t total;      // bytes
-    uint32_t nblk;     // compaction blocks
 };
 
 struct ro_cache {
@@ -141,6 +140,11 @@ ro_status stream_bricks_device(ro_cache *c, uint32_t frame, uint32_t n_new, uint
                                uint32_t *victims_host, uint32_t *evicted_host);
 ro_status read_requests_device(ro_cache *c, uint32_t cap, uint32_t *ids, uint32_t *counts,
                                uint32_t *n_unique, uint64_t *total, hipStream_t s);
+size_t compact_scratch_bytes(uint64_t n, uint32_t lim);
+ro_status compact_dense_ws(const VolGeo &g, uint32_t *arr, uint8_t *ws, uint32_t lim, uint32_t cap, uint32_t *ids,
+                           uint32_t *counts, uint32_t *n_unique, uint64_t *total, hipStream_t s);
+ro_status read_requests_noalloc_device(ro_cache *c, uint32_t cap, uint32_t *ids, uint32_t *counts,
+                                       uint32_t *n_unique, uint64_t *total, hipStream_t s);
 ro_status compact_dense(ro_cache *c, uint32_t *arr, uint32_t cap, uint32_t *ids, uint32_t *vals,
                         uint32_t *n_unique, uint64_t *total, hipStream_t s);
 ro_status cache_evict_channel(ro_cache *c, uint32_t ch, hipStream_t s);

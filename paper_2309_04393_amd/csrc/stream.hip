@@ -3,6 +3,8 @@
 // the CPU under a global limit; Sec. 5.3: slot selection with LRU eviction).
 #include <string.h>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace ro {
@@ -101,11 +103,13 @@ __global__ void __launch_bounds__(256) k_scan_blocks(const uint32_t *__restrict_
     if (threadIdx.x == 0) offs[nblk] = carry;
 }
 
-// Writes (ID, count) of every nonzero counter at its ascending rank and
-// clears the counter.
+// Writes the ID and count of every nonzero counter at its ascending rank r
+// (out_ids[r], out_vals[r], only for r < lim) and clears every nonzero
+// counter, whatever its rank.
 __global__ void __launch_bounds__(256) k_req_write(uint32_t *__restrict__ cnt, uint64_t n,
                                                    const uint32_t *__restrict__ offs, VolGeo g,
-                                                   uint32_t *__restrict__ pairs) {
+                                                   uint32_t *__restrict__ out_ids, uint32_t *__restrict__ out_vals,
+                                                   uint32_t lim) {
     __shared__ uint32_t lds[4];
     uint64_t base = (uint64_t)blockIdx.x * 1024 + threadIdx.x * 4;
     uint32_t v[4], nz = 0;
@@ -120,9 +124,10 @@ __global__ void __launch_bounds__(256) k_req_write(uint32_t *__restrict__ cnt, u
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (v[k]) {
-            uint32_t d = (uint32_t)(base + k);
-            pairs[2 * r] = dense_to_id(g, d);
-            pairs[2 * r + 1] = v[k];
+            if (r < lim) {
+                out_ids[r] = dense_to_id(g, (uint32_t)(base + k));
+                out_vals[r] = v[k];
+            }
             cnt[base + k] = 0;
             ++r;
         }
@@ -134,24 +139,33 @@ ro_status read_requests_device(ro_cache *c, uint32_t cap, uint32_t *ids, uint32_
     return compact_dense(c, c->b.counters, cap, ids, counts, n_unique, total, s);
 }
 
-// Compacts a dense per-brick u32 array into (ID, value) pairs of its nonzero
-// entries in ascending ID order (at most cap returned), with the distinct
-// count and the sum, and clears the array.  Synchronises.
-ro_status compact_dense(ro_cache *c, uint32_t *arr, uint32_t cap, uint32_t *ids, uint32_t *counts,
-                        uint32_t *n_unique, uint64_t *total, hipStream_t s) {
-    const VolGeo &g = c->vol->g;
-    uint8_t *sc = (uint8_t *)c->b.scratch;
-    uint32_t nblk = c->sc.nblk;
-    uint32_t *blk = (uint32_t *)(sc + c->sc.blk);
-    uint32_t *offs = blk + nblk + 1;
-    unsigned long long *tot = (unsigned long long *)(sc + c->sc.sel);
-    uint32_t *pairs = (uint32_t *)(sc + c->sc.outpairs);
-    RO_HIP(hipMemsetAsync(tot, 0, 8, s));
+// Work space of one compaction of n entries: nblk = ceil(n / 1024) block
+// counts, nblk + 1 offsets, the 64-bit sum, and lim output IDs and values.
+size_t compact_scratch_bytes(uint64_t n, uint32_t lim) {
+    const uint64_t nblk = (n + 1023) / 1024;
+    return 256 + (((2 * nblk + 1) * 4 + 255) / 256) * 256 + 2 * (((uint64_t)lim * 4 + 255) / 256) * 256;
+}
+
+// Compaction of the dense per-brick array arr (g.total entries) in the work
+// space ws (compact_scratch_bytes(g.total, lim) bytes, 256-byte aligned):
+// copies the first min(cap, lim) (ID, value) pairs in ascending ID order to
+// the host, with the distinct count and the sum, and clears the array.
+// Clears its counters with a fill kernel (no memset).  Synchronises.
+ro_status compact_dense_ws(const VolGeo &g, uint32_t *arr, uint8_t *ws, uint32_t lim, uint32_t cap, uint32_t *ids,
+                           uint32_t *counts, uint32_t *n_unique, uint64_t *total, hipStream_t s) {
+    const uint32_t nblk = (uint32_t)((g.total + 1023) / 1024);
+    unsigned long long *tot = (unsigned long long *)ws;
+    uint32_t *blk = (uint32_t *)(ws + 256);
+    uint32_t *offs = blk + nblk;
+    uint32_t *out_ids = (uint32_t *)(ws + 256 + (((2 * (uint64_t)nblk + 1) * 4 + 255) / 256) * 256);
+    uint32_t *out_vals = out_ids + (((uint64_t)lim * 4 + 255) / 256) * 64;
+    ro_status st = launch_fill_u32((uint32_t *)tot, 2, 0u, s);
+    if (st) return st;
     hipLaunchKernelGGL(k_req_count, dim3(nblk), dim3(256), 0, s, arr, g.total, blk, tot);
     RO_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, s, blk, nblk, offs);
     RO_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_req_write, dim3(nblk), dim3(256), 0, s, arr, g.total, offs, g, pairs);
+    hipLaunchKernelGGL(k_req_write, dim3(nblk), dim3(256), 0, s, arr, g.total, offs, g, out_ids, out_vals, lim);
     RO_HIP(hipGetLastError());
     uint32_t nu = 0;
     unsigned long long t = 0;
@@ -159,18 +173,75 @@ ro_status compact_dense(ro_cache *c, uint32_t *arr, uint32_t cap, uint32_t *ids,
     RO_HIP(hipMemcpyAsync(&t, tot, 8, hipMemcpyDeviceToHost, s));
     RO_HIP(hipStreamSynchronize(s));
     uint32_t k = nu < cap ? nu : cap;
+    k = k < lim ? k : lim;
     if (k) {
-        std::vector<uint32_t> tmp(2 * (size_t)k);
-        RO_HIP(hipMemcpyAsync(tmp.data(), pairs, 8 * (size_t)k, hipMemcpyDeviceToHost, s));
+        RO_HIP(hipMemcpyAsync(ids, out_ids, 4 * (size_t)k, hipMemcpyDeviceToHost, s));
+        RO_HIP(hipMemcpyAsync(counts, out_vals, 4 * (size_t)k, hipMemcpyDeviceToHost, s));
         RO_HIP(hipStreamSynchronize(s));
-        for (uint32_t i = 0; i < k; ++i) {
-            ids[i] = tmp[2 * i];
-            counts[i] = tmp[2 * i + 1];
-        }
     }
     *n_unique = nu;
     *total = t;
     return RO_OK;
+}
+
+// Compaction in the cache's own scratch buffer (room for every brick).
+ro_status compact_dense(ro_cache *c, uint32_t *arr, uint32_t cap, uint32_t *ids, uint32_t *counts,
+                        uint32_t *n_unique, uint64_t *total, hipStream_t s) {
+    const VolGeo &g = c->vol->g;
+    return compact_dense_ws(g, arr, (uint8_t *)c->b.scratch + c->sc.compact, (uint32_t)g.total, cap, ids, counts,
+                            n_unique, total, s);
+}
+
+// ------------------------------------- request readback without allocation
+
+// Fixed work space of ro_read_requests_noalloc: room for the compaction of
+// up to kNoAllocMaxBricks counters returning up to kNoAllocMaxPairs pairs.
+// One copy per GPU, held until the process ends; every call on a GPU uses
+// that GPU's copy, so calls that overlap on one GPU race.
+constexpr uint64_t kNoAllocMaxBricks = 1ull << 26;
+constexpr uint32_t kNoAllocMaxPairs = RO_NOALLOC_MAX_PAIRS;
+constexpr size_t kNoAllocBytes = 256 + (((2 * (kNoAllocMaxBricks / 1024) + 1) * 4 + 255) / 256) * 256 +
+                                 2 * (((size_t)kNoAllocMaxPairs * 4 + 255) / 256) * 256;
+
+}  // namespace ro
+
+static __device__ __align__(256) uint8_t scratch[ro::kNoAllocBytes];
+
+namespace ro {
+
+// Device address of this GPU's copy of `scratch` (the host-side name is not
+// a device address): taken once per device with that device current.
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static ro_status noalloc_scratch(uint8_t **out) {
+    int dev = -1;
+    RO_HIP(hipGetDevice(&dev));
+    RO_CHECK(dev >= 0 && dev < kMaxDevices, RO_E_DEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        RO_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        RO_CHECK(p != nullptr, RO_E_DEVICE, "no device address for the fixed work space");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (uint8_t *)g_scratch_ptr[dev];
+    return RO_OK;
+}
+
+ro_status read_requests_noalloc_device(ro_cache *c, uint32_t cap, uint32_t *ids, uint32_t *counts,
+                                       uint32_t *n_unique, uint64_t *total, hipStream_t s) {
+    const VolGeo &g = c->vol->g;
+    RO_CHECK(g.total <= kNoAllocMaxBricks, RO_E_CAPACITY,
+             "volume has %llu bricks; the fixed work space holds counters of at most %llu",
+             (unsigned long long)g.total, (unsigned long long)kNoAllocMaxBricks);
+    RO_CHECK(cap <= kNoAllocMaxPairs, RO_E_CAPACITY, "cap %u exceeds the fixed work space's %u pairs", cap,
+             kNoAllocMaxPairs);
+    uint8_t *ws = nullptr;
+    ro_status st = noalloc_scratch(&ws);
+    if (st) return st;
+    return compact_dense_ws(g, c->b.counters, ws, kNoAllocMaxPairs, cap, ids, counts, n_unique, total, s);
 }
 
 // -------------------------------------------------------- usage readback

@@ -26,6 +26,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 MAX_CHANNELS = 16
 MAX_LEVELS = 16
 INVALID = 0xFFFFFFFF
+NOALLOC_MAX_PAIRS = 262144  # RO_NOALLOC_MAX_PAIRS
 PROJ_ORTHO, PROJ_PERSP = 0, 1
 RENDER_NO_SKIP, RENDER_AOV, RENDER_ADAPTIVE_STEP, RENDER_HOMOGENEOUS = 1, 2, 4, 8
 
@@ -95,6 +96,7 @@ _sig("ro_cache_create", c_i32, [c_vp, _P(CacheDesc), _P(CacheBuffers), c_vp, _P(
 _sig("ro_cache_destroy", None, [c_vp])
 _sig("ro_stream_bricks", c_i32, [c_vp, c_u32, c_u32, c_vp, c_vp, c_vp, c_vp])
 _sig("ro_read_requests", c_i32, [c_vp, c_u32, c_vp, c_vp, _P(c_u32), _P(c_u64), c_vp])
+_sig("ro_read_requests_noalloc", c_i32, [c_vp, c_u32, c_vp, c_vp, _P(c_u32), _P(c_u64), c_vp])
 _sig("ro_read_usage", c_i32, [c_vp, c_u32, c_u32, c_vp, _P(c_u32), c_vp])
 _sig("ro_cache_evict_channel", c_i32, [c_vp, c_u32, c_vp])
 _sig("ro_cache_page_table_host", c_i32, [c_vp, c_vp, c_u64])
@@ -247,6 +249,16 @@ class Cache:
         nu, tot = c_u32(), c_u64()
         _check(_lib.ro_read_requests(self.h, cap, _np_ptr(ids), _np_ptr(cnt), ctypes.byref(nu),
                                      ctypes.byref(tot), _stream(stream)), "ro_read_requests")
+        k = min(cap, nu.value)
+        return ids[:k], cnt[:k], int(nu.value), int(tot.value)
+
+    def read_requests_noalloc(self, cap: int, stream=None):
+        """ro_read_requests_noalloc: the same readback with the library's fixed work space."""
+        ids = np.zeros(max(cap, 1), np.uint32)
+        cnt = np.zeros(max(cap, 1), np.uint32)
+        nu, tot = c_u32(), c_u64()
+        _check(_lib.ro_read_requests_noalloc(self.h, cap, _np_ptr(ids), _np_ptr(cnt), ctypes.byref(nu),
+                                             ctypes.byref(tot), _stream(stream)), "ro_read_requests_noalloc")
         k = min(cap, nu.value)
         return ids[:k], cnt[:k], int(nu.value), int(tot.value)
 
