@@ -133,6 +133,7 @@ class Frames:
         """One full step; returns (upload ids, staged tensor, missing)."""
         self.render(f)
         ids, tot, nu = self.plan()
+        self.last_nu = nu
         if staged is None:
             staged = self.s.stage(ids) if len(ids) else None
         if len(ids):
@@ -432,22 +433,58 @@ def adaptive_bench(scene, fl, frames, reps=3):
                              missing_samples=int(tot2), leaf_visits=int(st[3]),
                              lane_busy=float(st[0]) / max(float(st[5]), 1.0))
         row["speedup"] = row["plain"]["ms"] / row["adaptive"]["ms"]
+        # per-channel sampling rates (Sec. 6.1) with mixed per-channel level
+        # ranges (Sec. 6.2, Fig. 6): channel c at levels >= c mod 4; the mixed
+        # frame's working set is made resident first
+        mixed = [dict(ch, lo=min(c % 4, ch["hi"])) for c, ch in enumerate(fl.chans)]
+        for it in range(3):
+            scene.render(f, fl.cams[f], fl.W, fl.H, fl.step, mixed, tf_dev=fl.tf, out=fl.out,
+                         flags=resoct.RENDER_ADAPTIVE_STEP)
+            ids, cnt, nu, tot = scene.cache.read_requests(1 << 22)
+            if nu == 0:
+                break
+            order = np.lexsort((ids, -cnt.astype(np.int64)))
+            scene.upload(f, ids[order][: scene.cache.n_slots])
+            scene.tree.update_residency()
+            torch.cuda.synchronize()
+        for name, flags in (("mixed_ranges", resoct.RENDER_ADAPTIVE_STEP),
+                            ("mixed_ranges_channel_rates", resoct.RENDER_ADAPTIVE_STEP | resoct.RENDER_CHANNEL_RATES)):
+            ms = []
+            for _ in range(reps):
+                fl.stats.zero_()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                a.record()
+                scene.render(f, fl.cams[f], fl.W, fl.H, fl.step, mixed, tf_dev=fl.tf, out=fl.out,
+                             stats=fl.stats, flags=flags)
+                b.record()
+                torch.cuda.synchronize()
+                ms.append(a.elapsed_time(b))
+            st = fl.stats.cpu().numpy()
+            _, _, nu2, tot2 = scene.cache.read_requests(1 << 22)
+            row[name] = dict(ms=float(np.mean(ms)), samples=int(st[0]), channel_samples=int(st[1]),
+                             missing_samples=int(tot2), lane_busy=float(st[0]) / max(float(st[5]), 1.0))
+        row["channel_rates_speedup"] = row["mixed_ranges"]["ms"] / row["mixed_ranges_channel_rates"]["ms"]
+        row["channel_rates_read_ratio"] = (row["mixed_ranges_channel_rates"]["channel_samples"]
+                                           / max(row["mixed_ranges"]["channel_samples"], 1))
         out[str(f)] = row
         log(f"adaptive step, frame {f}: {row}")
     return out
 
 
 def homogeneous_bench(frames=(0, 12), reps=7, W=1920, H=1080, haze=0.05):
-    """Homogeneous leaves (RO_RENDER_HOMOGENEOUS) on a fully resident
-    4-channel 1024x1024x64 u16 cell volume whose leaf metadata are computed
-    on the GPU from the level-0 bricks (exact, so background leaves can be
-    homogeneous).  Channels 0 and 2 show a faint haze over the low values (a
-    table flat over its first nine entries), 1 and 3 are zero there.  Each
-    orbit frame is rendered plain and with the option, once untimed and then
-    `reps` times: median kernel time from HIP events, samples, brick reads,
-    distinct bricks read, and the largest image difference (zero where level
-    0 is read; homogeneous leaves read at coarse levels may differ from their
-    voxels' interpolation)."""
+    """Render-and-skip of nodes homogeneous for all channels
+    (RO_RENDER_HOMOGENEOUS) on a fully resident 4-channel 1024x1024x64 u16
+    cell volume whose leaf metadata are computed on the GPU from the level-0
+    bricks (exact, so the cell-free background has min == max == 0).
+    Channels 0 and 2 show a faint haze at the low values (value 0 is
+    visible), 1 and 3 are empty there, so background nodes are homogeneous
+    or empty in every channel.  Each orbit frame is rendered plain and with
+    the option, once untimed and then `reps` times: median kernel time from
+    HIP events, samples, brick reads, distinct bricks read, samples rendered
+    from homogeneous nodes, and the largest image difference (zero where
+    level 0 is read; a coarse level's interpolation may differ from the
+    node's value)."""
     import torch
     import synth
     from paper_2309_04393_amd import resoct
@@ -456,10 +493,8 @@ def homogeneous_bench(frames=(0, 12), reps=7, W=1920, H=1080, haze=0.05):
     t = time.perf_counter()
     n_all = resoct.Volume(vol.dims, vol.spacing, 4, 2, 32, vol.n_levels).brick_count()
     scene = GpuScene(vol, 32, (16, 16, 4), 6, n_all, max_batch=4096, set_metadata=False)
-    unknown = np.zeros((scene.tree.n_leaves, 2), np.uint16)
-    unknown[:, 1] = 65535
     for c in range(4):
-        scene.set_metadata(c, unknown)
+        scene.set_unknown(c)
     ids = scene.all_ids()
     scene.upload(0, ids)
     scene.tree.update_residency()
@@ -505,7 +540,7 @@ def homogeneous_bench(frames=(0, 12), reps=7, W=1920, H=1080, haze=0.05):
             _, nused = scene.cache.read_usage(fno)
             scene.cache.read_requests(1 << 22)
             row[name] = dict(ms=float(np.median(ms)), samples=int(st[0]), brick_reads=int(st[1]),
-                             bricks_read=int(nused), leaf_visits=int(st[3]))
+                             bricks_read=int(nused), leaf_visits=int(st[3]), homogeneous_samples=int(st[6]))
         row["speedup"] = row["plain"]["ms"] / row["homogeneous"]["ms"]
         row["image_max_abs_diff"] = float((img[0] - img[1]).abs().max().item())
         out[str(f)] = row
@@ -615,6 +650,61 @@ def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True, max_batch=64):
     return out
 
 
+def incremental_bench(n_frames=16, W=768, H=768, U=512):
+    """Incremental metadata (Alg. 1 reportNodeRequest, Sec. 5.3 without
+    server metadata) on the 4-channel 2048x2048x64 cell volume, orbit path
+    from a cold cache: the request-driven loop (render, plain policy, upload,
+    residency update) once with every leaf unknown and refined from the
+    inserted bricks, once with the server's metadata.  Per frame: kernel time
+    from HIP events, ray samples evaluated, samples skipped as empty space
+    (the base-step positions a lane skips), and the share of leaves with
+    metadata."""
+    import torch
+    import synth
+    from paper_2309_04393_amd.pipeline import GpuScene
+    vol = synth.config2_volume()
+    cams = synth.orbit_path(vol.dims, vol.spacing, n_frames)
+    chans = [dict(ch, hi=vol.n_levels - 1) for ch in channels(vol.n_channels, 2)]
+    out = {"workload": "4ch-2048x2048x64-u16 orbit, cold 27318-slot cache", "image": [W, H],
+           "upload_budget": U, "frames": n_frames}
+    for mode in ("unknown", "server"):
+        scene = GpuScene(vol, 32, (16, 16, 4), 7, 27318, max_batch=U, start_level=2,
+                         set_metadata=(mode == "server"))
+        if mode == "unknown":
+            for c in range(vol.n_channels):
+                scene.set_unknown(c)
+        tf = scene.tf_tensor(chans)
+        img = torch.empty(W * H * 4, dtype=torch.float32, device="cuda")
+        stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+        rows = []
+        for f in range(n_frames):
+            stats.zero_()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            scene.render(f + 1, cams[f], W, H, 0.5, chans, tf_dev=tf, out=img, stats=stats)
+            b.record()
+            torch.cuda.synchronize()
+            ids, cnt, nu, tot = scene.cache.read_requests(1 << 22)
+            order = np.lexsort((ids, -cnt.astype(np.int64)))
+            up = ids[order][:U]
+            if len(up):
+                flags = scene.upload(f + 1, up)
+                if mode == "unknown":
+                    scene.tree.leaf_metadata_from_bricks(up[flags == 1])
+            scene.tree.update_residency()
+            torch.cuda.synchronize()
+            st = stats.cpu().numpy()
+            row = dict(ms=a.elapsed_time(b), samples=int(st[0]), missing=int(tot), uploads=int(len(up)))
+            if mode == "unknown":
+                row["known_leaves"] = float((scene.tree.leaf_levels() < 255).mean())
+            rows.append(row)
+        out[mode] = rows
+        log(f"incremental metadata ({mode}): " + ", ".join(f"{r['ms']:.2f}" for r in rows) + " ms")
+        del scene
+        torch.cuda.empty_cache()
+    return out
+
+
 def prefetch_bench(train_seeds=tuple(range(1000, 1010)), eval_seeds=tuple(range(1010, 1015)), n_frames=120,
                    U=512, lr=3e-3, train_steps=4, threshold=0.5, gate=0.5):
     """Learned prefetcher against plain request-driven streaming on the
@@ -705,6 +795,8 @@ def main():
                          "the coarse bricks of zoomed-out frames take the host generator a while)")
     ap.add_argument("--no-homogeneous", action="store_true",
                     help="skip the homogeneous-leaves measurement (its own 4-channel scene)")
+    ap.add_argument("--no-incremental", action="store_true",
+                    help="skip the loop that starts from unknown leaf metadata")
     ap.add_argument("--prefetch-only", action="store_true",
                     help="only the learned-prefetcher evaluation (10 training, 5 held-out paths)")
     ap.add_argument("--pf-lr", type=float, default=3e-3)
@@ -769,10 +861,24 @@ def main():
     torch.cuda.synchronize()
     snap = snapshot(scene)
     # pass A: collect the uploads of the timed frames (untimed)
-    plans, store, usage, stats_a = [], [], [], []
+    plans, store, usage, stats_a, tree_reads, req_px, missed = [], [], [], [], [], [], []
+    nodes_t = torch.zeros(scene.tree.n_nodes, dtype=torch.uint8, device="cuda")
     for f in range(f0, f0 + K):
+        # diagnostic render of the frame (untimed, its own kernel): the nodes
+        # whose metadata the frame reads and the bricks each pixel requires;
+        # its miss counts are discarded and its stamps are the frame's own
+        nodes_t.zero_()
+        d = scene.render(f, fl.cams[f], fl.W, fl.H, fl.step, fl.chans, tf_dev=fl.tf, bricks=True, nodes=nodes_t)
+        torch.cuda.synchronize()
+        scene.cache.read_requests(1 << 22)
+        marked = nodes_t.cpu().numpy()
+        n_leaf = int(marked[scene.tree.n_nodes - scene.tree.n_leaves:].sum())
+        tree_reads.append((int(marked.sum()) - n_leaf, n_leaf))
+        req_px.append(d["bricks"].cpu().numpy().ravel())
+        del d
         fl.stats.zero_()
         ids, staged, tot = fl.step_frame(f)
+        missed.append(fl.last_nu)
         plans.append(ids.copy())
         store.append(staged)
         _, nused = scene.cache.read_usage(f)
@@ -804,8 +910,16 @@ def main():
     ms_step = (t1 - t0) * 1000.0 / K
     samples = int(st[0])
     ch_samples = int(st[1])
+    # algorithmic bytes of a launch: every brick read once (its voxels with the
+    # halo, its page-table entry, its stamp), the metadata (4 B per channel)
+    # of the inner nodes and the metadata and masks (6 B per channel) of the
+    # leaves the descents read, the image, and a read and write of the miss
+    # counter of each missed brick
     slot_bytes = (cfg["B"] + 2) ** 3 * 2
-    alg_bytes = [u * slot_bytes + cfg["W"] * cfg["H"] * 16 for u in usage]
+    m = vol.n_channels
+    alg_parts = [dict(bricks=u * (slot_bytes + 8), tree=ni * m * 4 + nl * m * 6, image=cfg["W"] * cfg["H"] * 16,
+                      counters=8 * nm) for u, (ni, nl), nm in zip(usage, tree_reads, missed)]
+    alg_bytes = [sum(p.values()) for p in alg_parts]
     mean_render_s = np.mean(render_ms) / 1000.0
     achieved = np.mean(alg_bytes) / mean_render_s / 1e9
     out = {
@@ -835,8 +949,15 @@ def main():
         "lane_busy": float(st[0]) / max(float(st[5]), 1.0),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(cfg["name"]),
-                     "kernel": "k_render", "alg_bytes_per_launch": float(np.mean(alg_bytes))},
+                     "kernel": "k_render", "alg_bytes_per_launch": float(np.mean(alg_bytes)),
+                     "alg_bytes_parts": {k: float(np.mean([p[k] for p in alg_parts])) for k in alg_parts[0]}},
     }
+    # bricks each pixel requires (Sec. 8, Fig. 8), over the timed frames
+    rp = np.concatenate(req_px)
+    out["required_bricks_per_pixel"] = {"mean": float(rp.mean()), "p50": float(np.percentile(rp, 50)),
+                                        "p99": float(np.percentile(rp, 99)), "max": int(rp.max()),
+                                        "tree_nodes_read_per_frame": float(np.mean([a + b for a, b in tree_reads])),
+                                        "leaves_read_per_frame": float(np.mean([b for _, b in tree_reads]))}
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
@@ -856,11 +977,17 @@ def main():
             out["cpu_baseline"] = cb
             win = img[y0:y0 + args.tile, x0:x0 + args.tile]
             ok = r["amb_pix"] == 0
-            d = np.abs(win - r["rgba"])[ok]
+            # a pixel with one close termination call has two valid values:
+            # compared with the nearer one
+            d = np.abs(win - r["rgba"])
+            da = np.abs(win - r["alt_rgba"])
+            use = (r["alt_pix"] != 0) & (da.max(axis=-1) < d.max(axis=-1))
+            d = np.where(use[..., None], da, d)[ok]
             out["parity"] = {"window": [x0, y0, args.tile, args.tile], "frame": fl_last,
                              "missing_samples_in_frame": int(stats_a[-1][2]),
                              "max_abs": d.max(axis=0).tolist(), "mean_abs": d.mean(axis=0).tolist(),
-                             "ambiguous_frac": float(1.0 - ok.mean())}
+                             "ambiguous_frac": float(1.0 - ok.mean()),
+                             "close_termination_frac": float((r["alt_pix"] != 0).mean())}
         except Exception as e:  # reported, not fatal
             out["cpu_baseline"] = {"error": repr(e)}
     # after the parity window, which reads the last timed frame's image
@@ -871,12 +998,15 @@ def main():
     if not args.no_adaptive:
         log("LOD-adaptive step on zoomed-out frames")
         out["adaptive_step"] = adaptive_bench(scene, fl, tuple(int(x) for x in args.adaptive_frames.split(",")))
-    if args.serve > 0 or not args.no_prefetch or not args.no_homogeneous:
+    if args.serve > 0 or not args.no_prefetch or not args.no_homogeneous or not args.no_incremental:
         del fl, store, scene
         torch.cuda.empty_cache()
     if not args.no_homogeneous:
         log("homogeneous leaves")
         out["homogeneous_leaves"] = homogeneous_bench()
+    if not args.no_incremental:
+        log("incremental metadata")
+        out["incremental_metadata"] = incremental_bench()
     if args.serve > 0:
         out["serving"] = serve_bench(args.rate, args.serve, max_batch=args.serve_max_batch)
     if not args.no_prefetch:

@@ -180,6 +180,26 @@ ro_status ro_read_requests_noalloc(ro_cache *c, uint32_t cap, uint32_t *ids_host
 ro_status ro_read_usage(ro_cache *c, uint32_t frame, uint32_t cap, uint32_t *slots_host,
                         uint32_t *n_out, void *stream);
 
+/* Checkpoint of the whole residency state (Sec. 4: the CPU holds the
+ * state it needs to restart the GPU side): page table, miss counters, slot
+ * map, LRU stamps and upload sequence numbers, node metadata, residency masks
+ * and node flags of the octree and its cache, the cache's host mirrors
+ * (page table, slot map, bricks awaiting a residency update, upload
+ * counter), and with RO_SNAPSHOT_SLOTS the slot contents (slot_stride x
+ * n_slots bytes).  ro_snapshot_size gives the blob size for the current
+ * state; ro_snapshot writes it to host memory (RO_E_CAPACITY if cap is
+ * smaller; *used = bytes written) and synchronises.  ro_restore brings an
+ * octree and its cache of the same shapes back to the snapshot's state
+ * (RO_E_ARG for a blob of another shape or size, nothing changed); without
+ * RO_SNAPSHOT_SLOTS the slots must still hold what they held at the
+ * snapshot.  Frames rendered after a restore are those rendered after the
+ * snapshot.  Synchronises. */
+#define RO_SNAPSHOT_SLOTS 1u
+ro_status ro_snapshot_size(const ro_octree *t, uint32_t flags, size_t *bytes);
+ro_status ro_snapshot(const ro_octree *t, uint32_t flags, void *host_blob, size_t cap, size_t *used,
+                      void *stream);
+ro_status ro_restore(ro_octree *t, const void *host_blob, size_t size, void *stream);
+
 /* Run-time channel exchange (Sec. 5.2: when another data channel takes a
  * cache channel's place, what the cache holds for the old one is no longer
  * valid).  Every resident brick of cache channel `channel` leaves the cache:
@@ -228,9 +248,11 @@ typedef struct {
 /*  node_meta   n_nodes * m uint32 (min | max << 16)
  *  node_mask   n_nodes * m uint16
  *  node_flags  n_nodes bytes (propagation work flags)
- *  scratch     leaf-update work list */
+ *  scratch     leaf-update work list
+ *  leaf_level  n_leaves * m bytes: where each leaf's metadata came from (0 the
+ *              server or level-0 bricks, l level-l bricks, 255 unknown) */
 typedef struct {
-    size_t node_meta, node_mask, node_flags, scratch;
+    size_t node_meta, node_mask, node_flags, scratch, leaf_level;
     uint64_t n_nodes, n_leaves;
     int32_t leaf_grid[3]; /* leaves per axis (padded) */
 } ro_octree_sizes;
@@ -240,11 +262,13 @@ typedef struct {
     uint16_t *node_mask;
     uint8_t *node_flags;
     void *scratch;
+    uint8_t *leaf_level;
 } ro_octree_buffers;
 
 ro_status ro_octree_query(const ro_volume *v, const ro_octree_desc *desc, ro_octree_sizes *out);
 
-/* Clears metadata (to [0, 0]), masks and flags.  The octree refers to the
+/* Clears metadata (to [0, 0]), masks and flags; every leaf's metadata level
+ * is 255 (unknown).  The octree refers to the
  * cache's page tables; destroy it before the cache. */
 ro_status ro_octree_create(ro_cache *c, const ro_octree_desc *desc,
                            const ro_octree_buffers *bufs, void *stream, ro_octree **out);
@@ -254,9 +278,17 @@ void ro_octree_destroy(ro_octree *t);
  * "Updating culling information"): leaf_minmax_dev[n_leaves][2] uint16
  * (min, max) over the padded leaf grid, x fastest.  Must be conservative
  * for every L0 voxel within one voxel of the leaf.  Inner nodes then get the
- * min of their children's minima and the max of their maxima. */
+ * min of their children's minima and the max of their maxima.  The leaves'
+ * metadata level becomes 0 (brick data do not replace them). */
 ro_status ro_octree_set_leaf_metadata(ro_octree *t, uint32_t channel,
                                       const uint16_t *leaf_minmax_dev, void *stream);
+
+/* Unknown leaves (Sec. 5.2: node information not yet initialised; Alg. 1
+ * reportNodeRequest): every leaf of the channel gets [0, max raw value],
+ * which no transfer function can call empty or homogeneous, and metadata
+ * level 255, so the first brick data covering it (ro_octree_leaf_metadata_
+ * from_bricks) give it metadata; inner nodes are reduced again. */
+ro_status ro_octree_set_leaf_unknown(ro_octree *t, uint32_t channel, void *stream);
 
 /* Leaf metadata computed from resident brick data (Sec. 5.3: a client whose
  * server has no metadata derives it from the voxels it fetched; the
@@ -268,10 +300,12 @@ ro_status ro_octree_set_leaf_metadata(ro_octree *t, uint32_t channel,
  * and clamped to the level's grid ([0, 0] if nothing is left): at level 0
  * exactly the conservative metadata ro_octree_set_leaf_metadata asks for; at
  * coarser levels an estimate from fewer voxels, which may miss extremes.
- * Where bricks of several levels cover one leaf, the finest level's values
- * stay.  Leaves outside the given bricks keep their metadata: to keep them
- * from being skipped before their data arrive, give them [0, max raw value]
- * first (unknown = never empty).  Inner nodes of the touched channels are
+ * A leaf takes a brick's values only when the brick's level is at most the
+ * leaf's metadata level, which then becomes the brick's level: metadata are
+ * refined by finer data and never replaced by coarser ones, across calls and
+ * within one.  Leaves outside the given bricks keep their metadata: to keep
+ * them from being skipped before their data arrive, make them unknown first
+ * (ro_octree_set_leaf_unknown).  Inner nodes of the touched channels are
  * then reduced again.  Reads the slots: call it after the ro_stream_bricks
  * that uploaded them, on the same stream or after it has completed.  Returns
  * after the work is queued (it waits for its own copies of the work list). */
@@ -296,7 +330,11 @@ ro_status ro_rebuild_residency(ro_octree *t, void *stream);
 #define RO_RENDER_NO_SKIP 1u /* evaluate every sample (results are identical) */
 #define RO_RENDER_AOV 2u     /* write per-pixel per-level sample counts to aov_dev */
 #define RO_RENDER_ADAPTIVE_STEP 4u /* LOD-adaptive sampling distance (see below) */
-#define RO_RENDER_HOMOGENEOUS 8u   /* homogeneous leaves rendered from their metadata (see below) */
+#define RO_RENDER_HOMOGENEOUS 8u   /* nodes homogeneous for all channels rendered from their values (see below) */
+#define RO_RENDER_BRICKS 16u       /* write the bricks each pixel requires to bricks_dev (see below) */
+#define RO_RENDER_CHANNEL_RATES 32u /* with the adaptive step: per-channel sampling rates (see below) */
+#define RO_RENDER_NODES 64u        /* mark the nodes whose metadata the frame reads in nodes_dev */
+#define RO_RENDER_TRAVERSAL_DEPTH 128u /* with the adaptive step: decision node from the step (see below) */
 
 /* One frame (Sec. 6.1, Alg. 1; Sec. 6.2).  Pixel (i, j), row 0 at the top,
  * has a = (2i+1-W)/W, b = (H-2j-1)/H.  Orthographic: origin
@@ -328,16 +366,37 @@ ro_status ro_rebuild_residency(ro_octree *t, void *stream);
  * only when k is a multiple of r (so skipping resumes on the same grid), and
  * its mixed opacity becomes 1 - (1 - alpha)^r with the premultiplied colour
  * scaled by the same factor.  Where l_s = 0 the frame is unchanged.
- * RO_RENDER_HOMOGENEOUS (Alg. 1 isHomogeneous / renderAndSkipNode, read
- * through the transfer function): a channel whose leaf is not empty and
- * whose interpolated table gives one RGBA for every value in the leaf's
- * [min, max] (a single value always does; a wider range when every table
- * entry reachable from it is identical) is sampled as the value min: it
- * reads no brick, requests nothing and stamps no slot, whatever is resident
- * and whatever level is desired.  Samples stay on the same grid and are
- * composited one by one, so early termination is unchanged.  Where level 0
- * is read and the metadata are exact, the image is the same as without the
- * option. */
+ * RO_RENDER_CHANNEL_RATES (Sec. 6.1: a channel may need only every second
+ * step; the channel needing the highest rate sets the step), only with
+ * RO_RENDER_ADAPTIVE_STEP and not with RO_RENDER_HOMOGENEOUS: channel c takes
+ * part in sample k only when k is a multiple of r_c, the x factor of its own
+ * desired level clamp(l*, lod_lo[c], lod_hi[c]); there it stands for r_c base
+ * steps, with transparency (1 - alpha_c)^r_c and colour weight r_c alpha_c,
+ * and the sample's opacity is 1 - prod of those transparencies (no further
+ * correction).  A channel's requests, reads and stamps come only from the
+ * samples it takes part in.  With one level range for every channel the
+ * frame is the adaptive one.
+ * RO_RENDER_TRAVERSAL_DEPTH (Alg. 1 chooseTraversalDepth: the tree is not
+ * traversed below a node the step would jump over), only with
+ * RO_RENDER_ADAPTIVE_STEP: a sample taken with step factor r decides
+ * emptiness and homogeneity at the deepest node whose smallest world extent
+ * is at least r * step (the leaf when the leaf is that large), so a channel
+ * not empty in that node samples its brick even where its own leaf is
+ * empty; requests and substitution stay per sample (leaf masks).  Where
+ * every step fits in a leaf the frame is the adaptive one.
+ * RO_RENDER_HOMOGENEOUS (Alg. 1 isHomogeneous / renderAndSkipNode; Sec. 6.1:
+ * a node is rendered from its value only when it is homogeneous for all
+ * channels): a channel is homogeneous in a node whose metadata hold one value
+ * (min == max).  A node in which every visible channel is empty or
+ * homogeneous, and at least one is homogeneous, is rendered from those values
+ * and skipped: each of its samples takes, per homogeneous channel, the node's
+ * value through the transfer function, mixed and composited like a sampled
+ * one; no brick is read, requested or stamped there, whatever is resident and
+ * whatever level is desired.  Samples stay on the same grid, so early
+ * termination falls on the same sample.  Every other node is rendered as
+ * without the option (a channel homogeneous in a node that is not is sampled
+ * from its brick).  Where level 0 is read and the metadata are exact, the
+ * image is the same as without the option. */
 typedef struct {
     uint32_t frame;     /* frame number written into slot stamps, < 0xFFFFFFFF */
     int32_t projection; /* RO_PROJ_ORTHO or RO_PROJ_PERSP */
@@ -363,7 +422,18 @@ typedef struct {
                                       [3] (leaf, level) visits, [4] channel samples in leaves
                                       that are not empty for the channel, [5] lane slots of
                                       the wave stepping iterations ([0] / [5] = share of
-                                      lanes busy); [6..7] zero */
+                                      lanes busy), [6] ray samples rendered from
+                                      homogeneous nodes; [7] zero */
+    uint32_t *bricks_dev; /* RO_RENDER_BRICKS: device [H][W][1 + n_vis] uint32; word 0 of a
+                             pixel receives the number of bricks the pixel requires (Sec. 8,
+                             bricks required to be resident per pixel): the distinct desired
+                             bricks (channel, l*, brick) of its samples in leaves where the
+                             channel is not empty, outside nodes rendered from their values,
+                             up to its early termination, resident or not; words 1..n_vis
+                             are the kernel's work space.  Needs no clearing. */
+    uint8_t *nodes_dev;   /* RO_RENDER_NODES: device [n_nodes] uint8, zeroed by the caller; every
+                             node whose metadata the frame's descents read gets 1 (the tree's
+                             part of the frame's memory traffic) */
 } ro_frame_desc;
 
 /* Renders into rgba_dev[H][W][4] (float, premultiplied) and updates the

@@ -51,7 +51,8 @@ class Frame(ctypes.Structure):
                 ("lod_hi", ctypes.c_int * MAXC), ("W0", ctypes.c_uint32 * MAXC),
                 ("W1", ctypes.c_uint32 * MAXC), ("tf", ctypes.c_void_p * MAXC),
                 ("term_alpha", ctypes.c_double), ("term_margin", ctypes.c_double), ("adaptive", ctypes.c_int),
-                ("homogeneous", ctypes.c_int)]
+                ("homogeneous", ctypes.c_int), ("channel_rates", ctypes.c_int),
+                ("traversal_depth", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -86,11 +87,9 @@ def lib():
         L.or_masks.argtypes = [PV, vp, vp]
         L.or_tf_empty.restype = ci
         L.or_tf_empty.argtypes = [ctypes.c_uint32] * 4 + [vp]
-        L.or_tf_flat.restype = ci
-        L.or_tf_flat.argtypes = [ctypes.c_uint32] * 4 + [vp]
         L.or_render.restype = ci
         L.or_render.argtypes = [PV, vp, vp, vp, vp, vp, ctypes.POINTER(Frame), ci, ci, vp, vp, vp, vp,
-                                vp, vp, vp, ctypes.POINTER(Stats), ci]
+                                vp, vp, vp, vp, vp, vp, ctypes.POINTER(Stats), ci]
         L.or_brute.restype = ci
         L.or_brute.argtypes = [PV, vp, ci, ctypes.POINTER(Frame), vp]
         L.or_plain_policy.restype = ci
@@ -161,7 +160,7 @@ def meta_all(V: Volume, leaf_mm: np.ndarray) -> np.ndarray:
     return out
 
 
-def leaf_meta_from_bricks(V: Volume, levels, leaf_mm: np.ndarray, brick_ids) -> np.ndarray:
+def leaf_meta_from_bricks(V: Volume, levels, leaf_mm: np.ndarray, brick_ids, leaf_level=None):
     """Sec. 5.3, metadata computed on the client from fetched brick voxels
     (plain numpy over the definition).  levels[c][l]: level arrays [z][y][x];
     leaf_mm: [C][n_leaves][2] before the call; brick_ids: IDs of the bricks
@@ -170,12 +169,18 @@ def leaf_meta_from_bricks(V: Volume, levels, leaf_mm: np.ndarray, brick_ids) -> 
     [min, max] of the voxels of the brick's level that overlap the leaf box
     grown by one voxel of that level, clamped to the level's grid ([0, 0] if
     nothing is left).  Bricks are applied coarsest level first, so where
-    several cover a leaf the finest level's values stay."""
+    several cover a leaf the finest level's values stay.  With leaf_level
+    ([C][n_leaves], where each leaf's metadata came from: 0 the server or
+    level-0 data, l level-l data, 255 unknown) a leaf takes a brick's values
+    only when the brick's level is at most its entry, which then becomes the
+    brick's level (finer data refine, coarser never replace); the result is
+    then (metadata, levels)."""
     d, f, nb = level_info(V)
     _, _, n = node_count(V)
     ng = [int(x) for x in n[V.depth]]
     lf = [int(x) for x in V.leaf]
     out = np.array(leaf_mm, dtype=np.uint16, copy=True)
+    lev = None if leaf_level is None else np.array(leaf_level, dtype=np.uint8, copy=True)
     bricks = sorted({brick_id_decode(V.n_levels, int(i)) for i in brick_ids}, key=lambda t: -t[1])
     for c, l, bx, by, bz in bricks:
         arr = levels[c][l]
@@ -193,13 +198,17 @@ def leaf_meta_from_bricks(V: Volume, levels, leaf_mm: np.ndarray, brick_ids) -> 
                         x0, x1, fa = li * lf[a], (li + 1) * lf[a], int(f[l][a])
                         box.append((max(x0 // fa - 1, 0), min((x1 - 1) // fa + 1, int(d[l][a]) - 1)))
                     k = (lz * ng[1] + ly) * ng[0] + lx
+                    if lev is not None:
+                        if l > lev[c, k]:
+                            continue
+                        lev[c, k] = l
                     if any(lo > hi for lo, hi in box):
                         out[c, k] = (0, 0)
                         continue
                     (x0, x1), (y0, y1), (z0, z1) = box
                     sub = arr[z0:z1 + 1, y0:y1 + 1, x0:x1 + 1]
                     out[c, k] = (sub.min(), sub.max())
-    return out
+    return out if lev is None else (out, lev)
 
 
 def masks(V: Volume, res_slot: np.ndarray) -> np.ndarray:
@@ -215,13 +224,8 @@ def tf_empty(mn, mx, W0, W1, tf) -> bool:
     return bool(lib().or_tf_empty(mn, mx, W0, W1, _p(t)))
 
 
-def tf_flat(mn, mx, W0, W1, tf) -> bool:
-    t = np.ascontiguousarray(tf, dtype=np.float32)
-    return bool(lib().or_tf_flat(mn, mx, W0, W1, _p(t)))
-
-
 def make_frame(cam: dict, W, H, delta, channels: list, term_alpha=0.99, lod_bias=1.0,
-               term_margin=1e-5, adaptive=False, homogeneous=False):
+               term_margin=1e-5, adaptive=False, homogeneous=False, channel_rates=False, traversal_depth=False):
     """channels: list of dicts {c, lo, hi, W0, W1, tf (256x4 float32)} in
     visible-slot order.  Returns (Frame, keepalive)."""
     fr = Frame()
@@ -236,6 +240,8 @@ def make_frame(cam: dict, W, H, delta, channels: list, term_alpha=0.99, lod_bias
     fr.term_margin = term_margin
     fr.adaptive = 1 if adaptive else 0
     fr.homogeneous = 1 if homogeneous else 0
+    fr.channel_rates = 1 if channel_rates else 0
+    fr.traversal_depth = 1 if traversal_depth else 0
     fr.nvis = len(channels)
     keep = []
     for j, ch in enumerate(channels):
@@ -282,7 +288,9 @@ def source_from_generator(gen):
 def render(V: Volume, levels, res_slot, leaf_mm, frame: Frame, n_slots: int, aov=False,
            n_threads=0, source: Source = None, rows=None, boxes=None):
     """O1.  Returns dict with rgba [H][W][4] f64, counts [dense] u32,
-    used [slots] u8, amb_pix, amb_counts, amb_used, aov, stats.  With
+    used [slots] u8, amb_pix, amb_counts, amb_used, alt_rgba / alt_pix (the
+    other outcome of one early-termination decision within the margin),
+    required_bricks [H][W] u32, aov, stats.  With
     `source` (and levels None) voxels come from the generator; `rows`
     = (row0, row1) restricts the frame to a band of rows; `boxes`
     [C][L][6] (origin, size) says that levels[c][l] holds only that window
@@ -298,6 +306,9 @@ def render(V: Volume, levels, res_slot, leaf_mm, frame: Frame, n_slots: int, aov
     amb_pix = np.zeros((H, W), np.uint8)
     amb_counts = np.zeros(nb, np.uint32)
     amb_used = np.zeros(max(n_slots, 1), np.uint8)
+    alt_rgba = np.zeros((H, W, 4), np.float64)
+    alt_pix = np.zeros((H, W), np.uint8)
+    reqb = np.zeros((H, W), np.uint32)
     aov_a = np.zeros((H, W, V.n_levels), np.uint32) if aov else None
     if levels is not None:
         ptrs, keep = _level_ptrs(V, levels)
@@ -310,10 +321,11 @@ def render(V: Volume, levels, res_slot, leaf_mm, frame: Frame, n_slots: int, aov
     rc = lib().or_render(ctypes.byref(V), ptrs, _p(bx), ctypes.byref(source) if source is not None else None,
                          _p(rs), _p(lm), ctypes.byref(frame), r0, r1, _p(rgba),
                          _p(counts), _p(used), _p(aov_a), _p(amb_pix), _p(amb_counts),
-                         _p(amb_used), ctypes.byref(st), n_threads)
+                         _p(amb_used), _p(alt_rgba), _p(alt_pix), _p(reqb), ctypes.byref(st), n_threads)
     assert rc == 0
     return dict(rgba=rgba, counts=counts, used=used[:n_slots], amb_pix=amb_pix,
                 amb_counts=amb_counts, amb_used=amb_used[:n_slots], aov=aov_a,
+                alt_rgba=alt_rgba, alt_pix=alt_pix, required_bricks=reqb,
                 stats=dict(samples=st.samples, channel_samples=st.channel_samples,
                            missing=st.missing, amb_samples=st.amb_samples,
                            amb_pixels=st.amb_pixels))

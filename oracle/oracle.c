@@ -314,30 +314,6 @@ int or_tf_empty(uint32_t mn, uint32_t mx, uint32_t W0, uint32_t W1, const float 
     return 1;
 }
 
-/* Homogeneity of a [mn, mx] raw range (Alg. 1 isHomogeneous, read through
- * the transfer function): the interpolated RGBA is the same for every value
- * in [mn, mx], with alpha non-zero.  A single value (mn == mx) always is
- * (alpha aside); a wider range is iff every table entry reachable from it
- * (the same set as for emptiness) holds the same RGBA, since the table is
- * interpolated linearly between entries.  Then the value mn stands for
- * every sample, and a sample there needs no voxel.  Exact integer
- * arithmetic. */
-int or_tf_flat(uint32_t mn, uint32_t mx, uint32_t W0, uint32_t W1, const float *tf /*256x4*/) {
-    if (mn == mx) return !or_tf_empty(mn, mx, W0, W1, tf);
-    long long den = (long long)W1 - (long long)W0;
-    long long nlo = 255LL * ((long long)mn * 256 - (long long)W0);
-    long long nhi = 255LL * ((long long)mx * 256 - (long long)W0);
-    long long lo = nlo <= 0 ? 0 : nlo / den;
-    long long hi = nhi <= 0 ? 0 : (nhi + den - 1) / den;
-    if (lo > 255) lo = 255;
-    if (hi > 255) hi = 255;
-    if (tf[4 * lo + 3] == 0.0f) return 0;
-    for (long long e = lo + 1; e <= hi; ++e)
-        for (int k = 0; k < 4; ++k)
-            if (tf[4 * e + k] != tf[4 * lo + k]) return 0;
-    return 1;
-}
-
 static void tf_eval(double v, uint32_t W0, uint32_t W1, const float *tf, double out[4]) {
     double w0 = W0 / 256.0, w1 = W1 / 256.0;
     double x = (v - w0) / (w1 - w0);
@@ -369,7 +345,9 @@ typedef struct {
     double term_alpha;
     double term_margin; /* |A - term_alpha| below this marks an ambiguous termination */
     int adaptive;       /* LOD-adaptive step (Sec. 6.1, the sampling distance grows with the level) */
-    int homogeneous;    /* homogeneous leaves rendered from their metadata (Alg. 1 renderAndSkipNode) */
+    int homogeneous;    /* leaves homogeneous for all channels rendered from their metadata (Alg. 1 renderAndSkipNode) */
+    int channel_rates;  /* with adaptive: each channel sampled at the rate of its own level (Sec. 6.1) */
+    int traversal_depth; /* with adaptive: emptiness decided at the node the step size allows (Alg. 1) */
 } or_frame;
 
 /* Level data: lvl[c * L + l] points to the level's array [z][y][x]
@@ -539,6 +517,11 @@ typedef struct {
 
 #define AMB_POS 1e-9
 
+static int cmp_ll(const void *a, const void *b) {
+    const long long x = *(const long long *)a, y = *(const long long *)b;
+    return x < y ? -1 : x > y;
+}
+
 /* O1: one frame.  Inputs: volume, level arrays, resident slots per dense
  * brick (-1 = not resident), leaf metadata leaf_mm[c][leaf][2], frame.
  * Outputs (any may be NULL):
@@ -549,9 +532,19 @@ typedef struct {
  *   used[slot]         1 if some sample read from the slot
  *   aov[H][W][L]       samples per level actually used
  *   amb_pix[H][W]      1 if the pixel has a sample within the ambiguity
- *                      margin or an early-termination decision within it
+ *                      margin, or a second early-termination decision within
+ *                      it
  *   amb_counts[dense]  requests of samples after an ambiguous termination
  *   amb_used[slot]     slots read by samples after an ambiguous termination
+ *   reqb[H][W]         bricks the pixel requires (Sec. 8, bricks required to
+ *                      be resident per pixel): the number of distinct desired
+ *                      bricks (c, l*, b*) of its samples that need data (a
+ *                      channel not empty in the sample's leaf, the leaf not
+ *                      rendered from its values), up to its termination
+ *   alt_rgba[H][W][4]  with alt_pix[H][W] = 1: the pixel's other valid
+ *                      value, had its one early-termination decision within
+ *                      the margin gone the other way (stopped there, or
+ *                      composited on to the next stop)
  * Every pixel's ray samples t_k = k delta, k = 0, 1, ...; samples outside
  * [0, dims) are void.  Early termination when A >= term_alpha.  With
  * Fr->adaptive only the samples on the grid of their level band are taken
@@ -559,8 +552,8 @@ typedef struct {
 int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, const or_source *src,
               const int32_t *res_slot, const uint16_t *leaf_mm, const or_frame *Fr, int row0,
               int row1, double *rgba, uint32_t *counts, uint8_t *used, uint32_t *aov,
-              uint8_t *amb_pix, uint32_t *amb_counts, uint8_t *amb_used, or_stats *stats,
-              int n_threads) {
+              uint8_t *amb_pix, uint32_t *amb_counts, uint8_t *amb_used, double *alt_rgba,
+              uint8_t *alt_pix, uint32_t *reqb, or_stats *stats, int n_threads) {
     geo_t G;
     tree_t T;
     geo(V, &G);
@@ -587,8 +580,38 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
         if (Fr->lod_lo[jv] < step_lo) step_lo = Fr->lod_lo[jv];
         if (Fr->lod_hi[jv] < step_hi) step_hi = Fr->lod_hi[jv];
     }
+    /* Traversal depth from the step (Alg. 1 chooseTraversalDepth: the tree is
+     * traversed no deeper than a node the step cannot jump over): with the
+     * option, a sample taken with step factor r decides emptiness and
+     * homogeneity on the deepest node whose smallest world extent is at
+     * least r delta (the leaf when the leaf is large enough), reading that
+     * node's metadata: min and max over the leaves inside it. */
+    uint16_t *node_mm = NULL;
+    int ddep[OR_MAXL];
+    for (int l = 0; l < OR_MAXL; ++l) ddep[l] = Dp;
+    if (Fr->adaptive && Fr->traversal_depth) {
+        node_mm = (uint16_t *)malloc((size_t)T.total * V->n_channels * 2 * sizeof(uint16_t));
+        if (!node_mm || or_meta_all(V, leaf_mm, node_mm)) {
+            free(node_mm);
+            return -1;
+        }
+        for (int l = 0; l < L; ++l) {
+            const double dist = G.f[l][0] * Fr->delta;
+            int d = Dp;
+            for (;;) {
+                double ext = INFINITY;
+                for (int a = 0; a < 3; ++a) ext = fmin(ext, T.size[d][a] * V->spacing[a]);
+                if (ext >= dist || d == 0) break;
+                --d;
+            }
+            ddep[l] = d;
+        }
+    }
     long long st_s = 0, st_cs = 0, st_m = 0, st_as = 0, st_ap = 0;
-    if (!lvl && !(src && src->fetch)) return -1;
+    if (!lvl && !(src && src->fetch)) {
+        free(node_mm);
+        return -1;
+    }
     if (row0 < 0) row0 = 0;
     if (row1 <= 0 || row1 > Fr->H) row1 = Fr->H;
 #ifdef _OPENMP
@@ -598,6 +621,8 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
     {
     sampler_t SM = {V, lvl, lvl_box, src, lvl ? NULL : new_tiles(), (const int(*)[3])G.dl,
                     (const int(*)[3])G.f, L};
+    long long *rkeys = NULL; /* desired bricks of the current pixel (with repeats) */
+    size_t nrk = 0, caprk = 0;
 #pragma omp for schedule(dynamic, 1)
     for (int j = row0; j < row1; ++j) {
         for (int i = 0; i < Fr->W; ++i) {
@@ -608,8 +633,14 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
              * reduced-precision renderer may have stopped (or not) there:
              * every later sample's requests and reads are tolerated.
              * shadow: this oracle has stopped compositing (A >= term) but
-             * keeps walking the ray to collect those tolerated sets. */
-            int pamb = 0, shadow = 0, tol = 0;
+             * keeps walking the ray to collect those tolerated sets.
+             * Both outcomes of that one decision are valid images of the
+             * pixel: the one not taken is kept as the alternate (Ca, Aa); when
+             * this oracle stopped there, the alternate goes on compositing
+             * (altrun) until its own termination. */
+            double Ca[3] = {0, 0, 0}, Aa = 0.0;
+            int pamb = 0, shadow = 0, tol = 0, alt = 0, altrun = 0;
+            nrk = 0;
             pixel_ray(V, Fr, i, j, o, d);
             if (box_interval(V, o, d, &t0, &t1)) {
                 long long k0 = (long long)floor(t0 / Fr->delta) - 1;
@@ -641,13 +672,14 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
                             if (fabs(t - Dl[l]) <= 1e-9 * Dl[l]) lamb = 1;
                         }
                     }
-                    int rstep = 1;
+                    int rstep = 1, dn = Dp;
                     if (Fr->adaptive) {
                         int ls = nlev;
                         if (ls < step_lo) ls = step_lo;
                         if (ls > step_hi) ls = step_hi;
                         if (ls > L - 1) ls = L - 1;
                         rstep = G.f[ls][0];
+                        dn = ddep[ls];
                         if (k % rstep != 0) {
                             /* not on this band's grid; a level decision close to
                              * its threshold may take it on another renderer */
@@ -658,20 +690,64 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
                     samb |= lamb;
                     if (samb && !tol) { pamb = 1; st_as++; }
                     if (!shadow) st_s++;
+                    /* Render-and-skip leaf (Alg. 1 isHomogeneous / renderAndSkipNode;
+                     * Sec. 6.1: only a node homogeneous for all channels is rendered
+                     * from its value): with the option on, when every visible channel
+                     * is empty in the leaf or has one value there (metadata
+                     * min == max), and at least one has a value, each such channel's
+                     * value stands for the sample; nothing is read, requested or
+                     * stamped, whatever is resident.  Otherwise every non-empty
+                     * channel, homogeneous or not, samples its brick. */
+                    /* the decision node's metadata of channel c: the leaf's, or with a
+                     * traversal depth above the leaves that node's */
+                    long long dnode = leaf;
+                    if (dn < Dp)
+                        dnode = T.off[dn] + ((long long)(iu[2] / T.size[dn][2]) * T.n[dn][1] + iu[1] / T.size[dn][1]) *
+                                                T.n[dn][0] +
+                                iu[0] / T.size[dn][0];
+#define DMM(c) (dn < Dp ? node_mm + (dnode * V->n_channels + (c)) * 2 : leaf_mm + ((long long)(c) * nleaf + leaf) * 2)
+                    int rskip = 0;
+                    if (Fr->homogeneous) {
+                        int anyv = 0;
+                        rskip = 1;
+                        for (int jv = 0; jv < Fr->nvis && rskip; ++jv) {
+                            const uint16_t *mm = DMM(Fr->vis[jv]);
+                            if (or_tf_empty(mm[0], mm[1], Fr->W0[jv], Fr->W1[jv], Fr->tf[jv])) continue;
+                            if (mm[0] == mm[1]) anyv = 1;
+                            else rskip = 0;
+                        }
+                        rskip = rskip && anyv;
+                    }
+                    /* Per-channel sampling rates (Sec. 6.1: a channel may need only every
+                     * second step; the channel needing the highest rate sets the step):
+                     * with the option, channel c takes part in sample k only when k is a
+                     * multiple of r_c, the x factor of its own clamped desired level, and
+                     * then stands for r_c base steps: transparency (1 - alpha_c)^r_c,
+                     * colour weight r_c alpha_c.  The sample's opacity is then
+                     * 1 - prod of those transparencies, with no further correction
+                     * (with every r_c = r this is the adaptive step's correction). */
+                    const int rates = Fr->adaptive && Fr->channel_rates;
                     double prod = 1.0, sa = 0.0, srgb[3] = {0, 0, 0};
                     for (int jv = 0; jv < Fr->nvis; ++jv) {
                         int c = Fr->vis[jv];
-                        const uint16_t *mm = leaf_mm + ((long long)c * nleaf + leaf) * 2;
+                        const uint16_t *mm = DMM(c);
                         if (or_tf_empty(mm[0], mm[1], Fr->W0[jv], Fr->W1[jv], Fr->tf[jv])) continue;
-                        if (Fr->homogeneous && or_tf_flat(mm[0], mm[1], Fr->W0[jv], Fr->W1[jv], Fr->tf[jv])) {
-                            /* the leaf's value stands for the sample: no brick,
-                             * no request, no read, whatever is resident */
-                            if (shadow) continue;
+                        int rc = 1;
+                        if (rates) {
+                            int lc = nlev;
+                            if (lc < Fr->lod_lo[jv]) lc = Fr->lod_lo[jv];
+                            if (lc > Fr->lod_hi[jv]) lc = Fr->lod_hi[jv];
+                            if (lc > L - 1) lc = L - 1;
+                            rc = G.f[lc][0];
+                            if (k % rc != 0) continue; /* not this channel's sample */
+                        }
+                        if (rskip) {
+                            if (shadow && !altrun) continue;
                             double rgbaH[4];
                             tf_eval((double)mm[0], Fr->W0[jv], Fr->W1[jv], Fr->tf[jv], rgbaH);
-                            prod *= (1.0 - rgbaH[3]);
-                            sa += rgbaH[3];
-                            for (int k2 = 0; k2 < 3; ++k2) srgb[k2] += rgbaH[3] * rgbaH[k2];
+                            prod *= rates ? pow(1.0 - rgbaH[3], (double)rc) : (1.0 - rgbaH[3]);
+                            sa += rc * rgbaH[3];
+                            for (int k2 = 0; k2 < 3; ++k2) srgb[k2] += rc * rgbaH[3] * rgbaH[k2];
                             continue;
                         }
                         int ls = nlev;
@@ -681,6 +757,13 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
                         int bs[3];
                         for (int a = 0; a < 3; ++a) bs[a] = iu[a] / (G.B * G.f[ls][a]);
                         long long want = dense(&G, c, ls, bs[0], bs[1], bs[2]);
+                        if (reqb && !shadow) {
+                            if (nrk == caprk) {
+                                caprk = caprk ? 2 * caprk : 1024;
+                                rkeys = (long long *)realloc(rkeys, caprk * sizeof(long long));
+                            }
+                            rkeys[nrk++] = want;
+                        }
                         if (res_slot[want] < 0) {
                             if (tol) {
                                 if (amb_counts) {
@@ -707,7 +790,7 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
                         if (lu < 0) continue;
                         if (tol) {
                             if (amb_used) __atomic_store_n(&amb_used[slot], 1, __ATOMIC_RELAXED);
-                            if (shadow) continue;
+                            if (shadow && !altrun) continue;
                         } else {
                             if (used) __atomic_store_n(&used[slot], 1, __ATOMIC_RELAXED);
                             if (aov) aov[pidx * L + lu]++;
@@ -719,24 +802,39 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
                         double rgbaC[4];
                         tf_eval(v, Fr->W0[jv], Fr->W1[jv], Fr->tf[jv], rgbaC);
                         double ac = rgbaC[3];
-                        prod *= (1.0 - ac);
-                        sa += ac;
-                        for (int k2 = 0; k2 < 3; ++k2) srgb[k2] += ac * rgbaC[k2];
+                        prod *= rates ? pow(1.0 - ac, (double)rc) : (1.0 - ac);
+                        sa += rc * ac;
+                        for (int k2 = 0; k2 < 3; ++k2) srgb[k2] += rc * ac * rgbaC[k2];
                     }
-                    if (shadow) continue;
+                    if (shadow && !altrun) continue;
                     /* mix: alpha_s = 1 - prod(1 - alpha_c);
                      * C_s = alpha_s * sum(alpha_c rgb_c) / sum(alpha_c) */
                     double as = 1.0 - prod;
-                    if (rstep > 1) as = 1.0 - pow(prod, (double)rstep);
+                    if (rstep > 1 && !rates) as = 1.0 - pow(prod, (double)rstep);
                     double Cs[3] = {0, 0, 0};
                     if (sa > 0.0)
                         for (int k2 = 0; k2 < 3; ++k2) Cs[k2] = as * srgb[k2] / sa;
+                    if (shadow) {
+                        /* the alternate outcome: composited on to its own stop */
+                        for (int k2 = 0; k2 < 3; ++k2) Ca[k2] += (1.0 - Aa) * Cs[k2];
+                        Aa += (1.0 - Aa) * as;
+                        if (fabs(Aa - Fr->term_alpha) < Fr->term_margin) pamb = 1; /* a second close call */
+                        if (Aa >= Fr->term_alpha) altrun = 0;
+                        continue;
+                    }
                     for (int k2 = 0; k2 < 3; ++k2) Cc[k2] += (1.0 - A) * Cs[k2];
                     A += (1.0 - A) * as;
-                    if (!tol && fabs(A - Fr->term_alpha) < Fr->term_margin) {
+                    if (fabs(A - Fr->term_alpha) < Fr->term_margin) {
                         /* a reduced-precision renderer may decide either way here */
-                        pamb = 1;
-                        tol = 1;
+                        if (!tol) {
+                            tol = 1;
+                            alt = 1;
+                            for (int k2 = 0; k2 < 3; ++k2) Ca[k2] = Cc[k2];
+                            Aa = A;
+                            altrun = A >= Fr->term_alpha; /* it stops here: the alternate goes on */
+                        } else {
+                            pamb = 1; /* a second close call: more than two outcomes */
+                        }
                     }
                     if (A >= Fr->term_alpha) {
                         if (!tol) break;
@@ -751,11 +849,28 @@ int or_render(const or_volume *V, const void *const *lvl, const int *lvl_box, co
                 rgba[pidx * 4 + 3] = A;
             }
             if (amb_pix) amb_pix[pidx] = (uint8_t)pamb;
+            if (reqb) {
+                qsort(rkeys, nrk, sizeof(long long), cmp_ll);
+                uint32_t nd = 0;
+                for (size_t q = 0; q < nrk; ++q)
+                    if (q == 0 || rkeys[q] != rkeys[q - 1]) nd++;
+                reqb[pidx] = nd;
+            }
+            if (alt_pix) alt_pix[pidx] = (uint8_t)(alt && !pamb);
+            if (alt_rgba) {
+                alt_rgba[pidx * 4 + 0] = Ca[0];
+                alt_rgba[pidx * 4 + 1] = Ca[1];
+                alt_rgba[pidx * 4 + 2] = Ca[2];
+                alt_rgba[pidx * 4 + 3] = Aa;
+            }
             if (pamb) st_ap++;
         }
     }
     free(SM.tiles);
+    free(rkeys);
     }
+#undef DMM
+    free(node_mm);
     if (stats) {
         stats->samples = st_s;
         stats->channel_samples = st_cs;

@@ -464,6 +464,7 @@ extern "C" ro_status ro_octree_query(const ro_volume *v, const ro_octree_desc *d
     o->node_mask = sizeof(uint16_t) * t.n_nodes * v->g.m;
     o->node_flags = t.n_nodes;
     o->scratch = 16 * 65536 + 256;  // leaf-update work items
+    o->leaf_level = t.n_leaves * v->g.m;
     return RO_OK;
 }
 
@@ -473,10 +474,10 @@ extern "C" ro_status ro_octree_create(ro_cache *c, const ro_octree_desc *d,
     TreeGeo t;
     ro_status st = tree_geometry(c->vol, d, t);
     if (st) return st;
-    RO_CHECK(b->node_meta && b->node_mask && b->node_flags && b->scratch, RO_E_ARG,
+    RO_CHECK(b->node_meta && b->node_mask && b->node_flags && b->scratch && b->leaf_level, RO_E_ARG,
              "null device buffer");
     RO_CHECK(aligned(b->node_meta) && aligned(b->node_mask) && aligned(b->node_flags) &&
-                 aligned(b->scratch),
+                 aligned(b->scratch) && aligned(b->leaf_level),
              RO_E_ARG, "device buffers must be 256-byte aligned");
     ro_octree *o = new (std::nothrow) ro_octree;
     RO_CHECK(o, RO_E_NOMEM, "out of host memory");
@@ -489,12 +490,133 @@ extern "C" ro_status ro_octree_create(ro_cache *c, const ro_octree_desc *d,
     uint64_t nm = t.n_nodes * (uint64_t)c->vol->g.m;
     ro_status r;
     if ((r = launch_fill_u32(b->node_meta, nm, 0, s)) || (r = launch_fill_u16(b->node_mask, nm, 0, s)) ||
-        (r = launch_fill_u8(b->node_flags, t.n_nodes, 0, s))) {
+        (r = launch_fill_u8(b->node_flags, t.n_nodes, 0, s)) ||
+        (r = launch_fill_u8(b->leaf_level, t.n_leaves * (uint64_t)c->vol->g.m, kLevelUnknown, s))) {
         delete o;
         return r;
     }
     *out = o;
     return RO_OK;
+}
+
+// ------------------------------------------------------------- checkpoint
+
+// Snapshot blob: header, the cache's host state (as ro_cache_save_state
+// writes it), then the device arrays in a fixed order.
+struct SnapHeader {
+    uint64_t magic;
+    uint64_t total, slots, nodes, slot_stride;
+    uint32_t m, flags;
+    uint64_t host_bytes;
+};
+static const uint64_t kSnapMagic = 0x3150414e53524full;  // "ORSNAP1"
+
+struct SnapPart {
+    void *dev;
+    size_t bytes;
+};
+
+static int snap_parts(const ro_octree *t, uint32_t flags, SnapPart *p) {
+    const ro_cache *c = t->cache;
+    const uint64_t total = c->vol->g.total, S = c->desc.n_slots, nn = t->t.n_nodes, m = (uint64_t)c->vol->g.m;
+    int n = 0;
+    p[n++] = {c->b.page_table, 4 * total};
+    p[n++] = {c->b.counters, 4 * total};
+    p[n++] = {c->b.slot_brick, 4 * S};
+    p[n++] = {c->b.stamps, 4 * S};
+    p[n++] = {c->b.seqs, 4 * S};
+    p[n++] = {t->b.node_meta, 4 * nn * m};
+    p[n++] = {t->b.node_mask, 2 * nn * m};
+    p[n++] = {t->b.node_flags, nn};
+    p[n++] = {t->b.leaf_level, (size_t)t->t.n_leaves * m};
+    if (flags & RO_SNAPSHOT_SLOTS) p[n++] = {c->b.slots, (size_t)c->vol->g.slot_stride * S};
+    return n;
+}
+
+extern "C" ro_status ro_snapshot_size(const ro_octree *t, uint32_t flags, size_t *bytes) {
+    RO_CHECK(t && bytes, RO_E_ARG, "null argument");
+    RO_CHECK(!(flags & ~RO_SNAPSHOT_SLOTS), RO_E_ARG, "unknown snapshot flags 0x%x", flags);
+    size_t host = 0;
+    ro_status st = ro_cache_state_size(t->cache, &host);
+    if (st) return st;
+    SnapPart p[10];
+    const int n = snap_parts(t, flags, p);
+    size_t b = sizeof(SnapHeader) + host;
+    for (int i = 0; i < n; ++i) b += p[i].bytes;
+    *bytes = b;
+    return RO_OK;
+}
+
+extern "C" ro_status ro_snapshot(const ro_octree *t, uint32_t flags, void *host_blob, size_t cap, size_t *used,
+                                 void *stream) {
+    size_t need = 0;
+    ro_status st = ro_snapshot_size(t, flags, &need);
+    if (st) return st;
+    RO_CHECK(host_blob && used, RO_E_ARG, "null argument");
+    RO_CHECK(cap >= need, RO_E_CAPACITY, "snapshot needs %zu bytes, the buffer holds %zu", need, cap);
+    const ro_cache *c = t->cache;
+    SnapHeader hd;
+    memset(&hd, 0, sizeof(hd));
+    hd.magic = kSnapMagic;
+    hd.total = c->vol->g.total;
+    hd.slots = c->desc.n_slots;
+    hd.nodes = t->t.n_nodes;
+    hd.slot_stride = c->vol->g.slot_stride;
+    hd.m = (uint32_t)c->vol->g.m;
+    hd.flags = flags;
+    st = ro_cache_state_size(c, &hd.host_bytes);
+    if (st) return st;
+    uint8_t *o = (uint8_t *)host_blob;
+    memcpy(o, &hd, sizeof(hd));
+    o += sizeof(hd);
+    st = ro_cache_save_state(c, o, hd.host_bytes);
+    if (st) return st;
+    o += hd.host_bytes;
+    hipStream_t s = (hipStream_t)stream;
+    SnapPart p[10];
+    const int n = snap_parts(t, flags, p);
+    for (int i = 0; i < n; ++i) {
+        RO_HIP(hipMemcpyAsync(o, p[i].dev, p[i].bytes, hipMemcpyDeviceToHost, s));
+        o += p[i].bytes;
+    }
+    RO_HIP(hipStreamSynchronize(s));
+    *used = need;
+    return RO_OK;
+}
+
+extern "C" ro_status ro_restore(ro_octree *t, const void *host_blob, size_t size, void *stream) {
+    RO_CHECK(t && host_blob, RO_E_ARG, "null argument");
+    RO_CHECK(size >= sizeof(SnapHeader), RO_E_ARG, "snapshot blob too small");
+    SnapHeader hd;
+    memcpy(&hd, host_blob, sizeof(hd));
+    ro_cache *c = t->cache;
+    RO_CHECK(hd.magic == kSnapMagic, RO_E_ARG, "not a snapshot blob");
+    RO_CHECK(hd.total == c->vol->g.total && hd.slots == c->desc.n_slots && hd.nodes == t->t.n_nodes &&
+                 hd.slot_stride == c->vol->g.slot_stride && hd.m == (uint32_t)c->vol->g.m,
+             RO_E_ARG, "snapshot was taken from an octree or cache of another shape");
+    RO_CHECK(!(hd.flags & ~RO_SNAPSHOT_SLOTS), RO_E_ARG, "unknown snapshot flags 0x%x", hd.flags);
+    SnapPart p[10];
+    const int n = snap_parts(t, hd.flags, p);
+    size_t dev_bytes = 0;
+    for (int k = 0; k < n; ++k) dev_bytes += p[k].bytes;
+    RO_CHECK(hd.host_bytes >= sizeof(StateHeader) && size == sizeof(hd) + hd.host_bytes + dev_bytes, RO_E_ARG,
+             "snapshot blob size %zu does not match its header", size);
+    const uint8_t *i = (const uint8_t *)host_blob + sizeof(hd);
+    // the host state is checked before anything changes
+    StateHeader sh;
+    memcpy(&sh, i, sizeof(sh));
+    RO_CHECK(sh.magic == kStateMagic && sh.total == c->pt_host.size() && sh.slots == c->slot_host.size() &&
+                 hd.host_bytes == sizeof(sh) + 4 * (sh.total + sh.slots + sh.dirty),
+             RO_E_ARG, "snapshot blob's cache state does not match this cache");
+    // device arrays, then the host mirrors
+    hipStream_t s = (hipStream_t)stream;
+    const uint8_t *d = i + hd.host_bytes;
+    for (int k = 0; k < n; ++k) {
+        RO_HIP(hipMemcpyAsync(p[k].dev, d, p[k].bytes, hipMemcpyHostToDevice, s));
+        d += p[k].bytes;
+    }
+    RO_HIP(hipStreamSynchronize(s));
+    return ro_cache_load_state(c, i, hd.host_bytes);
 }
 
 extern "C" void ro_octree_destroy(ro_octree *t) { delete t; }
@@ -504,6 +626,12 @@ extern "C" ro_status ro_octree_set_leaf_metadata(ro_octree *t, uint32_t channel,
     RO_CHECK(t && leaf_mm, RO_E_ARG, "null argument");
     RO_CHECK(channel < (uint32_t)t->cache->vol->g.m, RO_E_ARG, "channel %u out of range", channel);
     return octree_set_meta(t, channel, leaf_mm, (hipStream_t)stream);
+}
+
+extern "C" ro_status ro_octree_set_leaf_unknown(ro_octree *t, uint32_t channel, void *stream) {
+    RO_CHECK(t, RO_E_ARG, "null argument");
+    RO_CHECK(channel < (uint32_t)t->cache->vol->g.m, RO_E_ARG, "channel %u out of range", channel);
+    return octree_set_meta(t, channel, nullptr, (hipStream_t)stream);
 }
 
 extern "C" ro_status ro_octree_leaf_metadata_from_bricks(ro_octree *t, uint32_t n, const uint32_t *ids,
@@ -566,10 +694,19 @@ ro_status validate_frame(const ro_octree *t, const ro_frame_desc *fd, const floa
     RO_CHECK(fd->term_alpha > 0.0f && fd->term_alpha <= 1.0f, RO_E_ARG, "term_alpha not in (0, 1]");
     RO_CHECK(fd->frame != kInvalid, RO_E_ARG, "frame 0xFFFFFFFF is reserved");
     RO_CHECK(fd->start_level >= -1 && fd->start_level <= t->t.depth, RO_E_ARG, "bad start_level");
-    RO_CHECK(!(fd->flags & ~(RO_RENDER_NO_SKIP | RO_RENDER_AOV | RO_RENDER_ADAPTIVE_STEP | RO_RENDER_HOMOGENEOUS)),
+    RO_CHECK(!(fd->flags & ~(RO_RENDER_NO_SKIP | RO_RENDER_AOV | RO_RENDER_ADAPTIVE_STEP | RO_RENDER_HOMOGENEOUS |
+                             RO_RENDER_BRICKS | RO_RENDER_CHANNEL_RATES | RO_RENDER_NODES |
+                             RO_RENDER_TRAVERSAL_DEPTH)),
              RO_E_ARG,
              "unknown render flags 0x%x", fd->flags);
     RO_CHECK(!(fd->flags & RO_RENDER_AOV) || fd->aov_dev, RO_E_ARG, "AOV requested without buffer");
+    RO_CHECK(!(fd->flags & RO_RENDER_BRICKS) || fd->bricks_dev, RO_E_ARG, "required bricks requested without buffer");
+    RO_CHECK(!(fd->flags & RO_RENDER_NODES) || fd->nodes_dev, RO_E_ARG, "node marks requested without buffer");
+    RO_CHECK(!(fd->flags & RO_RENDER_CHANNEL_RATES) ||
+                 ((fd->flags & RO_RENDER_ADAPTIVE_STEP) && !(fd->flags & RO_RENDER_HOMOGENEOUS)),
+             RO_E_ARG, "per-channel rates need the adaptive step and exclude homogeneous nodes");
+    RO_CHECK(!(fd->flags & RO_RENDER_TRAVERSAL_DEPTH) || (fd->flags & RO_RENDER_ADAPTIVE_STEP), RO_E_ARG,
+             "a traversal depth from the step needs the adaptive step");
     uint32_t seen = 0;
     for (int j = 0; j < fd->n_vis; ++j) {
         RO_CHECK(fd->vis[j] >= 0 && fd->vis[j] < g.m, RO_E_ARG, "vis[%d] out of range", j);

@@ -16,6 +16,7 @@ constexpr int kMaxC = RO_MAX_CHANNELS;
 constexpr int kMaxL = RO_MAX_LEVELS;
 constexpr int kMaxD = RO_MAX_DEPTH;
 constexpr int kMaxRuns = 128;  // zero-alpha runs of a 256-entry table
+constexpr uint32_t kLevelUnknown = 255;  // leaf metadata level of unknown leaves
 
 // Geometry of the bricked hierarchy (host and device copies are identical
 // plain structs passed by value).

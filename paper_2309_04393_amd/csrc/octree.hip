@@ -8,12 +8,16 @@
 namespace ro {
 
 // Leaf metadata of one channel -> node_meta of the leaf level.
-__global__ void k_meta_leaf(const uint16_t *__restrict__ leaf_mm, uint32_t *__restrict__ meta, uint64_t n_leaves,
-                            uint32_t leaf_off, int m, int c) {
+// Leaf metadata of channel c: from the caller's [n_leaves][2] array (level
+// 0), or, with leaf_mm null, unknown ([0, unknown_max], level unknown).
+__global__ void k_meta_leaf(const uint16_t *__restrict__ leaf_mm, uint32_t *__restrict__ meta,
+                            uint8_t *__restrict__ level, uint64_t n_leaves, uint32_t leaf_off, int m, int c,
+                            uint32_t unknown_max) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_leaves) return;
-    const uint32_t mn = leaf_mm[2 * i], mx = leaf_mm[2 * i + 1];
+    const uint32_t mn = leaf_mm ? leaf_mm[2 * i] : 0u, mx = leaf_mm ? leaf_mm[2 * i + 1] : unknown_max;
     meta[((uint64_t)leaf_off + i) * m + c] = mn | (mx << 16);
+    level[i * m + c] = leaf_mm ? 0 : (uint8_t)kLevelUnknown;
 }
 
 // Child index range of a level-d node: children per axis are 1 or 2.
@@ -90,7 +94,8 @@ struct MetaItem {
 __global__ __launch_bounds__(256) void k_meta_from_bricks(VolGeo g, TreeGeo t, const MetaItem *__restrict__ items,
                                                           uint32_t n_items, uint32_t w0, uint32_t n_work,
                                                           const uint8_t *__restrict__ slots,
-                                                          uint32_t *__restrict__ meta) {
+                                                          uint32_t *__restrict__ meta,
+                                                          uint8_t *__restrict__ level) {
     const uint32_t w = w0 + blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (w >= n_work) return;  // whole waves leave together
@@ -104,6 +109,10 @@ __global__ __launch_bounds__(256) void k_meta_from_bricks(VolGeo g, TreeGeo t, c
     const uint32_t r = w - it.start;
     const uint32_t leaf[3] = {it.x0 + r % it.nx, it.y0 + (r / it.nx) % it.ny, it.z0 + r / (it.nx * it.ny)};
     const int l = (int)it.l;
+    // metadata from finer data stay (the whole wave leaves together)
+    const uint64_t li = ((((uint64_t)leaf[2] << t.nlog[t.depth][1]) + leaf[1]) << t.nlog[t.depth][0]) + leaf[0];
+    uint8_t *lev = level + li * (uint64_t)g.m + it.c;
+    if (*lev < (uint8_t)l) return;
     int vlo[3], vn[3];
     bool empty = false;
 #pragma unroll
@@ -139,15 +148,19 @@ __global__ __launch_bounds__(256) void k_meta_from_bricks(VolGeo g, TreeGeo t, c
     } else {
         mn = 0;
     }
-    if (lane == 0)
+    if (lane == 0) {
         meta[(uint64_t)node_index(t, t.depth, leaf[0], leaf[1], leaf[2]) * g.m + it.c] = mn | (mx << 16);
+        *lev = (uint8_t)l;
+    }
 }
 
 ro_status octree_set_meta(ro_octree *tr, uint32_t c, const uint16_t *leaf_mm, hipStream_t s) {
     const TreeGeo &t = tr->t;
-    const int m = tr->cache->vol->g.m;
+    const VolGeo &g = tr->cache->vol->g;
+    const int m = g.m;
+    const uint32_t unknown_max = g.bpv == 1 ? 255u : 65535u;
     hipLaunchKernelGGL(k_meta_leaf, dim3(nblocks(t.n_leaves)), dim3(256), 0, s, leaf_mm, tr->b.node_meta,
-                       t.n_leaves, t.noff[t.depth], m, (int)c);
+                       tr->b.leaf_level, t.n_leaves, t.noff[t.depth], m, (int)c, unknown_max);
     RO_HIP(hipGetLastError());
     for (int d = t.depth - 1; d >= 0; --d) {
         const uint64_t n = 1ull << (t.nlog[d][0] + t.nlog[d][1] + t.nlog[d][2]);
@@ -338,7 +351,8 @@ ro_status octree_rebuild(ro_octree *tr, hipStream_t s) {
 // bricks' voxels (Sec. 5.3, metadata on the client when the server has
 // none).  `dense` holds validated resident dense indices sorted by level,
 // coarsest first, so that where bricks of several levels cover one leaf the
-// finest level's pass runs last and its values stay.
+// finest level's pass runs last and its values stay; a leaf whose metadata
+// came from finer data (its level entry) keeps them.
 ro_status octree_meta_from_bricks(ro_octree *tr, const std::vector<uint32_t> &dense, hipStream_t s) {
     if (dense.empty()) return RO_OK;
     const VolGeo &g = tr->cache->vol->g;
@@ -358,7 +372,8 @@ ro_status octree_meta_from_bricks(ro_octree *tr, const std::vector<uint32_t> &de
             const uint64_t nw = std::min(kChunk, work - w0);
             hipLaunchKernelGGL(k_meta_from_bricks, dim3((unsigned)((nw + 3) / 4)), dim3(256), 0, s, g, t,
                                (const MetaItem *)tr->b.scratch, (uint32_t)items.size(), (uint32_t)w0,
-                               (uint32_t)work, (const uint8_t *)tr->cache->b.slots, tr->b.node_meta);
+                               (uint32_t)work, (const uint8_t *)tr->cache->b.slots, tr->b.node_meta,
+                               tr->b.leaf_level);
             RO_HIP(hipGetLastError());
         }
         // the host buffer must outlive the copy: wait before reuse

@@ -56,9 +56,8 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
     __shared__ uint32_t s_runs[NV * kMaxRuns];
     __shared__ LevLds s_lv[kMaxL];
     __shared__ NodeLds s_nd[kMaxD + 1];
-    __shared__ uint32_t s_flat[HOMOG ? NV * (kMaxFlat + 1) : 1];  // runs of identical table entries
 
-    stage_frame<NV>(A, s_tf, s_ch, s_runs, s_lv, s_nd, HOMOG ? s_flat : nullptr);
+    stage_frame<NV>(A, s_tf, s_ch, s_runs, s_lv, s_nd);
 
     BlockQueue q;
     q.counter = counter;
@@ -70,13 +69,13 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
     q.W = A.W;
     q.H = A.H;
     q.min_idle = RO_MIN_IDLE;
-    uint32_t st[6] = {0, 0, 0, 0, 0, 0};
+    uint32_t st[7] = {0, 0, 0, 0, 0, 0, 0};
     const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
-    render_rays<NV, BPV, AOV, EC, EC == 0, HOMOG>(A, q, s_tf, s_ch, s_runs, s_lv, s_nd, s_flat, st, sl);
+    render_rays<NV, BPV, AOV, EC, EC == 0, HOMOG>(A, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
     if (A.stats) {
         // every lane of the workgroup is here: reduce over the wave, one atomic per wave
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
+        for (int j = 0; j < 7; ++j) {
             uint32_t v = st[j];
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -104,8 +103,8 @@ static hipError_t launch_one(const RenderArgs &A, const QueueLaunch &Q, hipStrea
 
 // Compile-time brick edges: 32^3 and 16^3 bricks with their halo (the AOV
 // diagnostic output and the LOD-adaptive step take the generic kernel).
-// Homogeneous leaves have instantiations of their own, so the kernels that
-// do not take them carry none of their code.
+// Render-and-skip of homogeneous nodes has instantiations of its own, so the
+// kernels that do not take it carry none of its code.
 template <int NV, int BPV>
 static hipError_t launch_nv(const RenderArgs &A, bool aov, const QueueLaunch &Q, hipStream_t s) {
     if (aov) return launch_one<NV, BPV, true, 0, true>(A, Q, s);
@@ -193,6 +192,23 @@ ro_status build_render_args(ro_octree *tr, const ro_frame_desc *fd, float *rgba,
             A.K[l] = kk < 0xFFFFFFFFll ? (uint32_t)kk : kInvalid;
         }
     }
+    // traversal depth from the step (Alg. 1 chooseTraversalDepth): for the
+    // step of level l, the deepest node whose smallest world extent is at
+    // least the distance between samples, f_l * step
+    for (int l = 0; l < kMaxL; ++l) A.dd[l] = (uint32_t)T.depth;
+    if ((fd->flags & RO_RENDER_TRAVERSAL_DEPTH) && (fd->flags & RO_RENDER_ADAPTIVE_STEP)) {
+        for (int l = 0; l < g.L; ++l) {
+            const double dist = (double)(1 << g.lshift[l][0]) * fd->step;
+            int d = T.depth;
+            while (d > 0) {
+                double ext = INFINITY;
+                for (int a = 0; a < 3; ++a) ext = fmin(ext, (double)(1ll << T.nshift[d][a]) * g.spacing[a]);
+                if (ext >= dist) break;
+                --d;
+            }
+            A.dd[l] = (uint32_t)d;
+        }
+    }
     A.nvis = fd->n_vis;
     A.ident = fd->n_vis == g.m && g.m % 4 == 0;
     for (int j = 0; j < fd->n_vis; ++j) A.ident = A.ident && fd->vis[j] == j;
@@ -224,7 +240,9 @@ ro_status build_render_args(ro_octree *tr, const ro_frame_desc *fd, float *rgba,
     A.mask = tr->b.node_mask;
     A.tf = (const float4 *)fd->tf_dev;
     A.rgba = rgba;
-    A.aov = fd->aov_dev;
+    A.aov = (fd->flags & RO_RENDER_AOV) ? fd->aov_dev : nullptr;
+    A.reqb = (fd->flags & RO_RENDER_BRICKS) ? fd->bricks_dev : nullptr;
+    A.nodes = (fd->flags & RO_RENDER_NODES) ? fd->nodes_dev : nullptr;
     A.stats = fd->stats_dev;
     return RO_OK;
 }
@@ -249,7 +267,8 @@ ro_status render_device(ro_octree *tr, const ro_frame_desc *fd, float *rgba, hip
     static_assert(RO_QUEUES * kQueueStride * 4 <= 256, "queue counters exceed the scratch tail");
     st = launch_fill_u32(Q.counter, (uint64_t)RO_QUEUES * kQueueStride, 0u, s);
     if (st) return st;
-    const bool aov = (fd->flags & RO_RENDER_AOV) != 0;
+    // the diagnostic outputs (per-level reads, required bricks) take the AOV kernel
+    const bool aov = (fd->flags & (RO_RENDER_AOV | RO_RENDER_BRICKS | RO_RENDER_NODES)) != 0;
     RO_HIP(g.bpv == 1 ? launch_bpv<1>(A, aov, Q, s) : launch_bpv<2>(A, aov, Q, s));
     return RO_OK;
 }

@@ -31,6 +31,7 @@ struct RenderArgs {
     uint32_t loff[kMaxL];  // brick offset of the level inside a channel
     uint32_t nbx[kMaxL], nby[kMaxL];
     uint32_t K[kMaxL];     // level l is desired from sample index K[l] on
+    uint32_t dd[kMaxL];    // traversal depth for the step of level l (the tree depth without the option)
     uint32_t nsh[kMaxD + 1];   // per tree level: packed log2 node edge
     uint32_t nlg[kMaxD + 1];   // per tree level: packed log2 node count
     uint32_t noff[kMaxD + 1];  // node offset of the level
@@ -43,7 +44,9 @@ struct RenderArgs {
     const uint16_t *mask;
     const float4 *tf;
     float *rgba;
-    uint32_t *aov;
+    uint32_t *aov;   // per-level reads (AOV kernel), or null
+    uint32_t *reqb;  // required bricks per pixel, [H][W][1 + nvis] (AOV kernel), or null
+    uint8_t *nodes;  // nodes whose metadata the frame reads, [n_nodes] (AOV kernel), or null
     unsigned long long *stats;
 };
 
@@ -58,6 +61,7 @@ struct LevLds {
     uint32_t sh;   // packed shifts (level factor + brick) per axis
     uint32_t raw;  // packed level factor shifts
     uint32_t loff, nbx, nbxy, K;
+    uint32_t dd;   // decision depth when this level sets the step
 };
 
 struct NodeLds {
@@ -101,44 +105,23 @@ __device__ __forceinline__ bool range_empty(uint32_t mm, const uint32_t *runs, i
     return false;
 }
 
-// Runs of identical, non-zero-alpha table entries as raw-value bounds
-// (lo | hi << 16, the same window arithmetic as build_runs): a range
-// [mn, mx] with mn < mx gives one interpolated RGBA iff some run has
-// mn >= lo and mx <= hi.  Only runs of two or more entries and single
-// entries at either end can hold such a range (a strictly increasing table
-// position is constant only where it is clamped), so at most 129 are kept.
-constexpr int kMaxFlat = 130;
-constexpr uint32_t kHomTag = 0x80000000u;  // slot word of a homogeneous channel: tag | leaf minimum (slots < 2^31)
-__device__ inline int build_flat_runs(const float4 *tf, uint32_t W0, uint32_t W1, uint32_t *runs) {
-    int n = 0, e = 0;
-    const uint64_t den = (uint64_t)W1 - (uint64_t)W0;
-    while (e < 256) {
-        const float4 t = tf[e];
-        const int a = e;
-        while (e + 1 < 256 && tf[e + 1].x == t.x && tf[e + 1].y == t.y && tf[e + 1].z == t.z &&
-               tf[e + 1].w == t.w)
-            ++e;
-        const int b = e++;
-        if (t.w == 0.0f || (a == b && a != 0 && a != 255)) continue;
-        uint64_t rlo = a == 0 ? 0 : (255ull * W0 + (uint64_t)a * den + 65279ull) / 65280ull;
-        uint64_t rhi = b == 255 ? 65535ull : (255ull * W0 + (uint64_t)b * den) / 65280ull;
-        if (rhi > 65535ull) rhi = 65535ull;
-        if (rlo <= rhi && n < kMaxFlat) runs[n++] = (uint32_t)rlo | ((uint32_t)rhi << 16);
-    }
-    return n;
-}
-
-// Homogeneity of a non-empty channel's [min, max] (frame option
-// RO_RENDER_HOMOGENEOUS): one interpolated RGBA over the whole range.  A
-// single value always qualifies.
-__device__ __forceinline__ bool range_flat(uint32_t mm, const uint32_t *runs, int nr) {
-    const uint32_t mn = mm & 0xFFFFu, mx = mm >> 16;
-    if (mn == mx) return true;
-    for (int r = 0; r < nr; ++r) {
-        const uint32_t q = runs[r];
-        if (mn >= (q & 0xFFFFu) && mx <= (q >> 16)) return true;
-    }
-    return false;
+// Transfer function of a visible channel at raw value v: window, table
+// position, linear interpolation of the LDS table (tf = the channel's 256
+// entries).
+__device__ __forceinline__ void classify(float v, const ChanLds &ch, const float4 *tf, float &al, float &r, float &g,
+                                         float &b) {
+    float x = (v - ch.w0) * ch.iw;
+    x = fminf(fmaxf(x, 0.0f), 1.0f);
+    const float p = x * 255.0f;
+    int e = (int)p;
+    e = e > 255 ? 255 : e;
+    const int e1i = e < 255 ? e + 1 : 255;
+    const float f = p - (float)e;
+    const float4 ta = tf[e], tb = tf[e1i];
+    al = ta.w + (tb.w - ta.w) * f;
+    r = ta.x + (tb.x - ta.x) * f;
+    g = ta.y + (tb.y - ta.y) * f;
+    b = ta.z + (tb.z - ta.z) * f;
 }
 
 // Two horizontally adjacent voxels (x, x + 1) in one load; the voxel grid
@@ -312,14 +295,13 @@ __host__ __device__ constexpr size_t slot_bytes(int e, int bpv) {
 
 // EC: the brick edge with halo known at compile time (0: read from A).  A
 // constant edge turns the four gather offsets into instruction immediates.
-// ADAPT / HOMOG: whether the LOD-adaptive step / homogeneous leaves are
-// compiled in (frames that ask for them go to a kernel that has them; with
-// HOMOG, s_flat holds each channel's runs of identical table entries).
+// ADAPT / HOMOG: whether the LOD-adaptive step / render-and-skip of nodes
+// homogeneous for all channels are compiled in (frames that ask for them go
+// to a kernel that has them).
 template <int NV, int BPV, bool AOV, int EC, bool ADAPT, bool HOMOG, class Source>
 __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, const float4 *s_tf,
                                             const ChanLds *s_ch, const uint32_t *s_runs, const LevLds *s_lv,
-                                            const NodeLds *s_nd, const uint32_t *s_flat, uint32_t stats[6],
-                                            LdsSlots slot) {
+                                            const NodeLds *s_nd, uint32_t stats[7], LdsSlots slot) {
     const int nvis = A.nvis;
     const int D = A.depth;
     const int L = A.L;
@@ -331,9 +313,15 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     const bool noskip = (A.flags & RO_RENDER_NO_SKIP) != 0;
     const bool adaptive = ADAPT && (A.flags & RO_RENDER_ADAPTIVE_STEP) != 0;
     const bool homog = HOMOG && (A.flags & RO_RENDER_HOMOGENEOUS) != 0;
+    // per-channel sampling rates (with the adaptive step): a channel takes part
+    // only in samples k that are multiples of its own level's x factor
+    const bool rates = ADAPT && adaptive && (A.flags & RO_RENDER_CHANNEL_RATES) != 0;
+    // traversal depth from the step (with the adaptive step): emptiness and
+    // homogeneity are decided at the node of depth dd of the step's level
+    const bool tdepth = ADAPT && adaptive && (A.flags & RO_RENDER_TRAVERSAL_DEPTH) != 0;
     const NodeLds leafl = s_nd[D];
     const bool single = s_ch[0].single != 0;
-    uint32_t st_samples = 0, st_reads = 0, st_miss = 0, st_visits = 0, st_nonempty = 0, st_iters = 0;
+    uint32_t st_samples = 0, st_reads = 0, st_miss = 0, st_visits = 0, st_nonempty = 0, st_iters = 0, st_hom = 0;
 
     // ---- per-ray state
     int px = 0, py = 0;
@@ -347,14 +335,17 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     uint32_t cur_leaf = kInvalid;
     int cur_lod = -1, lod = 0;
     uint32_t emask = 0, missmask = 0;
-    // channels homogeneous in the current leaf (set at each visit, not kept
-    // across samples): their slot word holds kHomTag | the leaf minimum
-    uint32_t hmask = 0;
+    // render-and-skip node (Alg. 1 renderAndSkipNode): samples k < hom_to lie
+    // in a node where every visible channel is empty or has one value; they
+    // composite the mix of those values (h_*), computed once per node
+    long long hom_to = 0;
+    float h_prod = 1.0f, h_sa = 0.0f, h_sr = 0.0f, h_sg = 0.0f, h_sb = 0.0f;
     uint64_t lvpack = 0;
     uint32_t nvisit = 0;
     int lc[3] = {-1, -1, -1};  // L0 origin of the last visited leaf (none yet)
     uint32_t last_key = kInvalid;  // (level, cell) of the last visit when uniform
     uint32_t have = 0;             // channels with a slot from the last visit
+    uint32_t stamped = 0;          // with rates: channels whose current slot carries this frame's stamp
 
     // ray set-up in L0 voxel units, box interval, first sample index
     auto start = [&](int x, int y, bool valid) {
@@ -390,6 +381,12 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         Cr = Cg = Cb = 0.0;
         Tr = 1.0;
         out = valid ? A.rgba + ((size_t)py * A.W + px) * 4 : nullptr;
+        if (AOV && A.reqb && valid) {
+            // required bricks: the count, then each channel's last desired brick
+            uint32_t *rb = A.reqb + ((size_t)py * A.W + px) * (1 + nvis);
+            rb[0] = 0;
+            for (int j = 0; j < nvis; ++j) rb[1 + j] = kInvalid;
+        }
         double t0 = -INFINITY, t1 = INFINITY;
         bool hit = true;
 #pragma unroll
@@ -418,12 +415,13 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         rpace = 0;
         while (lod + 1 < L && (unsigned long long)k >= s_lv[lod + 1].K) ++lod;
         emask = missmask = 0;
-        hmask = 0;
+        hom_to = 0;
         lvpack = 0;
         nvisit = 0;
         lc[0] = lc[1] = lc[2] = -1;
         last_key = kInvalid;
         have = 0;
+        stamped = 0;
 #pragma unroll
         for (int j = 0; j < NV; ++j) slot[j] = kInvalid;
     };
@@ -521,9 +519,11 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         // LOD-adaptive step: the finest desired level over the visible
         // channels sets the sampling distance, r = its x factor; only samples
         // with k a multiple of r are evaluated
-        int rsh = 0;
+        int rsh = 0, dend = D;
         if (adaptive) {
-            rsh = (int)field(s_lv[min(max(lod, A.step_lo), A.step_hi)].raw, 0);
+            const LevLds slv = s_lv[min(max(lod, A.step_lo), A.step_hi)];
+            rsh = (int)field(slv.raw, 0);
+            if (tdepth) dend = (int)slv.dd;
             rpace = rsh;
             const long long rm = (1ll << rsh) - 1;
             if (k & rm) {
@@ -531,19 +531,29 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 continue;
             }
         }
-        const uint32_t leaf = node_at(leafl, iu[0] >> field(leafl.nsh, 0), iu[1] >> field(leafl.nsh, 1),
-                                      iu[2] >> field(leafl.nsh, 2));
-        if (leaf != cur_leaf || lod != cur_lod) {
+        // inside a render-and-skip node: the node's constant mix stands for
+        // the sample (no descent, no lookup, no brick)
+        bool hs = HOMOG && k < hom_to;
+        uint32_t leaf = kInvalid;
+        if (!hs) leaf = node_at(leafl, iu[0] >> field(leafl.nsh, 0), iu[1] >> field(leafl.nsh, 1),
+                                iu[2] >> field(leafl.nsh, 2));
+        if (!hs && (leaf != cur_leaf || lod != cur_lod)) {
             flush();
-            if (leaf != cur_leaf) {
+            // with a traversal depth the decision node depends on the level too
+            if (leaf != cur_leaf || (tdepth && lod != cur_lod)) {
                 // Descend from the start level and skip the first node that
                 // is empty for every visible channel (the leaf included).
                 // Every ancestor of a visited leaf is non-empty, so levels
                 // whose node also holds the last visited leaf are known
                 // non-empty and the test starts below them (the same node
-                // is skipped either way).
-                int d0 = noskip ? D : s0;
-                if (lc[0] >= 0 && !noskip) {
+                // is skipped either way).  With HOMOG the first node in which
+                // every visible channel is empty or holds one value (and one
+                // holds a value) is rendered from those values and skipped
+                // (Alg. 1 renderAndSkipNode, Sec. 6.1: homogeneous for all
+                // channels); ancestors of a visited leaf are never such nodes
+                // either (metadata nest, so their descendants would be).
+                int d0 = noskip ? dend : min(s0, dend);
+                if (lc[0] >= 0 && !noskip && !tdepth) {
                     while (d0 < D) {
                         const uint32_t sh = s_nd[d0].nsh;
                         if (((iu[0] ^ lc[0]) >> field(sh, 0)) | ((iu[1] ^ lc[1]) >> field(sh, 1)) |
@@ -553,13 +563,14 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     }
                 }
                 bool skipped = false;
-                for (int dl = d0; dl <= D; ++dl) {
+                for (int dl = d0; dl <= dend; ++dl) {
                     const NodeLds nd = s_nd[dl];
                     const uint32_t node = node_at(nd, iu[0] >> field(nd.nsh, 0), iu[1] >> field(nd.nsh, 1),
                                                   iu[2] >> field(nd.nsh, 2));
                     // the node's metadata, kGroup channels per batch of loads
                     uint32_t em = 0, hm = 0;
                     const uint32_t *nm = A.meta + (size_t)node * m;
+                    if (AOV && A.nodes) A.nodes[node] = 1;
 #pragma unroll
                     for (int g = 0; g < NV; g += kGroup) {
                         if (g >= nvis) break;
@@ -589,24 +600,22 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                                 if (j < nvis && range_empty(mm[jj], s_runs + j * kMaxRuns, s_ch[j].nruns)) em |= 1u << j;
                             }
                         }
+                        if (homog) {
+#pragma unroll
+                            for (int jj = 0; jj < kGroup; ++jj) {
+                                const int j = g + jj;
+                                if (j < nvis && (mm[jj] & 0xFFFFu) == (mm[jj] >> 16)) hm |= 1u << j;
+                            }
+                        }
                         asm volatile("" ::: "memory");
                     }
-                    if (homog && dl == D) {
-                        // the leaf's non-empty channels, one at a time (a
-                        // rolled loop keeps the unrolled metadata loads' registers free)
-                        uint32_t cand = vismask & ~em;
-                        while (cand) {
-                            const int j = __builtin_ctz(cand);
-                            cand &= cand - 1u;
-                            const uint32_t *fl = s_flat + j * (kMaxFlat + 1);
-                            if (range_flat(nm[s_ch[j].c], fl + 1, (int)fl[0])) hm |= 1u << j;
-                        }
-                    }
-                    if (dl == D) {
-                        emask = em;
-                        hmask = hm;
-                    }
-                    if (em == (1u << nvis) - 1u && !noskip) {
+                    hm &= ~em;
+                    if (dl == dend) emask = em;
+                    const bool all_empty = em == vismask;
+                    const bool rskip = homog && hm && (em | hm) == vismask;
+                    // (without skipping, empty nodes are stepped through;
+                    // render-and-skip changes the image, so it stays on)
+                    if ((all_empty && !noskip) || rskip) {
                         double te = INFINITY;
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
@@ -617,9 +626,30 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                             te = fmin(te, (bound - o[a]) / d[a]);
                         }
                         const long long kn = (long long)floor(te / A.step) - 1;
-                        skip_to = kn > k + 1 ? kn : k + 1;
-                        ++k;
-                        skipped = true;
+                        if (all_empty) {
+                            skip_to = kn > k + 1 ? kn : k + 1;
+                            ++k;
+                            skipped = true;
+                        } else {
+                            // the samples up to the node's exit take the node's
+                            // values, mixed in visible-channel order as sampled
+                            // values are
+                            hom_to = kn > k + 1 ? kn : k + 1;
+                            h_prod = 1.0f;
+                            h_sa = h_sr = h_sg = h_sb = 0.0f;
+                            for (int j = 0; j < nvis; ++j) {
+                                if (!((hm >> j) & 1u)) continue;
+                                const ChanLds ch = s_ch[j];
+                                float al, r, gg, bb;
+                                classify((float)(nm[ch.c] & 0xFFFFu), ch, s_tf + j * 256, al, r, gg, bb);
+                                h_prod *= 1.0f - al;
+                                h_sa += al;
+                                h_sr += al * r;
+                                h_sg += al * gg;
+                                h_sb += al * bb;
+                            }
+                            hs = true;
+                        }
                         break;
                     }
                 }
@@ -627,35 +657,15 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     cur_leaf = kInvalid;
                     continue;
                 }
-                cur_leaf = leaf;
+                if (hs) {
+                    cur_leaf = kInvalid;
+                } else {
+                    cur_leaf = leaf;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) lc[a] = (iu[a] >> field(leafl.nsh, a)) << field(leafl.nsh, a);
-                if constexpr (HOMOG) {
-                    if (homog) {
-                        // the new leaf's homogeneous channels carry its minimum
-                        // in their slot word (the lookups below keep such words);
-                        // tags of the previous leaf go
-                        for (int j = 0; j < nvis; ++j) {
-                            const uint32_t sw = slot[j];
-                            if ((hmask >> j) & 1u)
-                                slot[j] = kHomTag | (A.meta[(size_t)leaf * m + s_ch[j].c] & 0xFFFFu);
-                            else if (sw != kInvalid && (sw & kHomTag))
-                                slot[j] = kInvalid;
-                        }
-                    }
-                }
-            } else {
-                if constexpr (HOMOG) {
-                    if (homog) {
-                        // same leaf, new level: the homogeneous channels are the tagged slot words
-                        hmask = 0;
-                        for (int j = 0; j < nvis; ++j) {
-                            const uint32_t sw = slot[j];
-                            if (sw != kInvalid && (sw & kHomTag)) hmask |= 1u << j;
-                        }
-                    }
+                    for (int a = 0; a < 3; ++a) lc[a] = (iu[a] >> field(leafl.nsh, a)) << field(leafl.nsh, a);
                 }
             }
+            if (!hs) {
             cur_lod = lod;
             ++st_visits;
             missmask = 0;
@@ -681,7 +691,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 all_at = ((andm >> lsu) & 1u) != 0;
             }
             if (all_at) {
-                look = vismask & ~emask & ~hmask;
+                look = vismask & ~emask;
                 lvpack = 0;
 #pragma unroll
                 for (int j = 0; j < NV; ++j)
@@ -704,7 +714,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 #pragma unroll
                     for (int jj = 0; jj < kGroup; ++jj) {
                         const int j = g + jj;
-                        if (j < nvis && !(((emask | hmask) >> j) & 1u)) {
+                        if (j < nvis && !((emask >> j) & 1u)) {
                             const ChanLds ch = s_ch[j];
                             const int ls = min(max(lod, ch.lo), ch.hi);
                             const uint32_t mj = mk[jj] >> ls;
@@ -751,14 +761,6 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     for (int jj = 0; jj < kGroup; ++jj) {
                         const int j = g + jj;
                         ns[jj] = kInvalid;
-                        if constexpr (HOMOG) {
-                            // a homogeneous channel keeps a tagged word (a real
-                            // slot of an earlier leaf is dropped)
-                            if (j < nvis && ((hmask >> j) & 1u)) {
-                                const uint32_t sw = slot[j];
-                                if (sw != kInvalid && (sw & kHomTag)) ns[jj] = sw;
-                            }
-                        }
                         if ((look >> j) & 1u) {
                             if ((reuse >> j) & 1u) {
                                 ns[jj] = slot[j];
@@ -775,14 +777,15 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     for (int jj = 0; jj < kGroup; ++jj) {
                         const int j = g + jj;
                         if (j >= nvis) break;
-                        bool no_slot;
-                        if constexpr (HOMOG) no_slot = ns[jj] >= kHomTag;  // none, or a tagged word
-                        else no_slot = ns[jj] == kInvalid;
-                        if (no_slot) {
+                        if (ns[jj] == kInvalid) {
                             lvpack &= ~((uint64_t)15u << (4 * j));
                         } else {
                             nhave |= 1u << j;
-                            if (ns[jj] != slot[j]) A.stamp[ns[jj]] = A.frame;
+                            if (ns[jj] != slot[j]) {
+                                // with rates the stamp waits for a sample the channel takes part in
+                                if (rates) stamped &= ~(1u << j);
+                                else A.stamp[ns[jj]] = A.frame;
+                            }
                         }
                         slot[j] = ns[jj];
                     }
@@ -791,17 +794,76 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
             }
             have = nhave;
             last_key = key;
+            }
         }
-        ++nvisit;
         ++st_samples;
-        st_nonempty += __popc(vismask & ~emask);
+        float prod = 1.0f, sa = 0.0f, sr = 0.0f, sg = 0.0f, sbl = 0.0f;
+        if (hs) {
+            ++st_hom;
+            prod = h_prod;
+            sa = h_sa;
+            sr = h_sr;
+            sg = h_sg;
+            sbl = h_sb;
+        } else {
+        // channels taking part in this sample (all of them without rates)
+        uint32_t part = vismask;
+        if (rates) {
+            part = 0;
+            for (int j = 0; j < nvis; ++j) {
+                const ChanLds ch = s_ch[j];
+                const int rs = (int)field(s_lv[min(max(lod, ch.lo), ch.hi)].raw, 0);
+                if (!(k & ((1ll << rs) - 1))) part |= 1u << j;
+            }
+            // misses and stamps per sample (a visit's samples differ in which
+            // channels take part)
+            uint32_t mp = missmask & part;
+            while (mp) {
+                const int j = __builtin_ctz(mp);
+                mp &= mp - 1u;
+                const ChanLds ch = s_ch[j];
+                const LevLds lv = s_lv[min(max(lod, ch.lo), ch.hi)];
+                atomicAdd(&A.cnt[brick_dense(lv, (uint32_t)ch.c, A.per_channel, iu[0] >> field(lv.sh, 0),
+                                             iu[1] >> field(lv.sh, 1), iu[2] >> field(lv.sh, 2))],
+                          1u);
+                ++st_miss;
+            }
+            uint32_t sp = have & part & ~stamped;
+            while (sp) {
+                const int j = __builtin_ctz(sp);
+                sp &= sp - 1u;
+                A.stamp[slot[j]] = A.frame;
+            }
+            stamped |= have & part;
+        } else {
+            ++nvisit;
+        }
+        if (AOV && A.reqb) {
+            // Bricks required per pixel: the desired brick of each channel not
+            // empty here that takes part in the sample (a leaf lies in one
+            // brick per level).  Along a ray the desired level never decreases
+            // and a brick's samples are one interval, so each required brick is
+            // one run of equal keys: count the changes.
+            uint32_t *rb = A.reqb + ((size_t)py * A.W + px) * (1 + nvis);
+            for (int j = 0; j < nvis; ++j) {
+                if (((emask >> j) & 1u) || !((part >> j) & 1u)) continue;
+                const ChanLds ch = s_ch[j];
+                const LevLds lv = s_lv[min(max(lod, ch.lo), ch.hi)];
+                const uint32_t key = brick_dense(lv, 0u, 0u, iu[0] >> field(lv.sh, 0), iu[1] >> field(lv.sh, 1),
+                                                 iu[2] >> field(lv.sh, 2));
+                if (rb[1 + j] != key) {
+                    rb[1 + j] = key;
+                    rb[0] += 1;
+                }
+            }
+        }
+        st_nonempty += __popc(vismask & ~emask & part);
         // ---- sample every visible channel
         // In-brick coordinates depend only on the level a channel samples
         // (bricks of one level share their grid), so they are computed once
         // per distinct level of the sample.  Channels are gathered in groups
         // of kGroup: the group's loads are all issued before any of them is
         // used, and two horizontally adjacent voxels come in one load.
-        float prod = 1.0f, sa = 0.0f, sr = 0.0f, sg = 0.0f, sbl = 0.0f;
         int lprev = -1;
         uint32_t idx = 0;
         float fr0 = 0.0f, fr1 = 0.0f, fr2 = 0.0f;
@@ -816,8 +878,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 #pragma unroll
             for (int jj = 0; jj < kGroup; ++jj) {
                 const int j = g + jj;
-                if constexpr (HOMOG) ok[jj] = j < nvis && slot[j] < kHomTag;
-                else ok[jj] = j < nvis && slot[j] != kInvalid;
+                ok[jj] = j < nvis && slot[j] != kInvalid && ((part >> j) & 1u);
                 const int lu = (int)((lvpack >> (4 * j)) & 15u);
                 if (ok[jj] && lu != lprev) {
                     const LevLds lv = s_lv[lu];
@@ -853,80 +914,52 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 #pragma unroll
             for (int jj = 0; jj < kGroup; ++jj) {
                 const int j = g + jj;
-                float v;
-                if constexpr (HOMOG) {
-                    // a homogeneous channel takes the leaf's minimum (every
-                    // value of the leaf's range maps to the same table result)
-                    uint32_t sw = kInvalid;
-                    if (!ok[jj]) {
-                        if (!homog || j >= nvis) continue;
-                        sw = slot[j];
-                        if (sw == kInvalid || !(sw & kHomTag)) continue;
-                    }
-                    if (ok[jj]) {
-                        const float f0 = fq[jj][0], f1 = fq[jj][1], f2 = fq[jj][2];
-                        float v00[2], v10[2], v01[2], v11[2];
-                        unpack<BPV>(w[jj][0], v00);
-                        unpack<BPV>(w[jj][1], v10);
-                        unpack<BPV>(w[jj][2], v01);
-                        unpack<BPV>(w[jj][3], v11);
-                        const float c00 = v00[0] + (v00[1] - v00[0]) * f0;
-                        const float c10 = v10[0] + (v10[1] - v10[0]) * f0;
-                        const float c01 = v01[0] + (v01[1] - v01[0]) * f0;
-                        const float c11 = v11[0] + (v11[1] - v11[0]) * f0;
-                        const float e0 = c00 + (c10 - c00) * f1;
-                        const float e1 = c01 + (c11 - c01) * f1;
-                        v = e0 + (e1 - e0) * f2;
-                        ++st_reads;
-                        if (AOV) A.aov[((size_t)py * A.W + px) * L + (int)((lvpack >> (4 * j)) & 15u)] += 1;
-                    } else {
-                        v = (float)(sw & 0xFFFFu);
-                    }
+                if (!ok[jj]) continue;
+                const float f0 = fq[jj][0], f1 = fq[jj][1], f2 = fq[jj][2];
+                float v00[2], v10[2], v01[2], v11[2];
+                unpack<BPV>(w[jj][0], v00);
+                unpack<BPV>(w[jj][1], v10);
+                unpack<BPV>(w[jj][2], v01);
+                unpack<BPV>(w[jj][3], v11);
+                const float c00 = v00[0] + (v00[1] - v00[0]) * f0;
+                const float c10 = v10[0] + (v10[1] - v10[0]) * f0;
+                const float c01 = v01[0] + (v01[1] - v01[0]) * f0;
+                const float c11 = v11[0] + (v11[1] - v11[0]) * f0;
+                const float e0 = c00 + (c10 - c00) * f1;
+                const float e1 = c01 + (c11 - c01) * f1;
+                const float v = e0 + (e1 - e0) * f2;
+                float al, r, gg, bb;
+                classify(v, s_ch[j], s_tf + j * 256, al, r, gg, bb);
+                ++st_reads;
+                if (rates) {
+                    // the channel stands for r_c base steps: transparency
+                    // (1 - alpha)^r_c, colour weight r_c alpha
+                    const ChanLds ch = s_ch[j];
+                    const int rs = (int)field(s_lv[min(max(lod, ch.lo), ch.hi)].raw, 0);
+                    float tr = 1.0f - al;
+                    for (int q = 0; q < rs; ++q) tr *= tr;
+                    const float w = (float)(1 << rs) * al;
+                    prod *= tr;
+                    sa += w;
+                    sr += w * r;
+                    sg += w * gg;
+                    sbl += w * bb;
                 } else {
-                    if (!ok[jj]) continue;
-                    const float f0 = fq[jj][0], f1 = fq[jj][1], f2 = fq[jj][2];
-                    float v00[2], v10[2], v01[2], v11[2];
-                    unpack<BPV>(w[jj][0], v00);
-                    unpack<BPV>(w[jj][1], v10);
-                    unpack<BPV>(w[jj][2], v01);
-                    unpack<BPV>(w[jj][3], v11);
-                    const float c00 = v00[0] + (v00[1] - v00[0]) * f0;
-                    const float c10 = v10[0] + (v10[1] - v10[0]) * f0;
-                    const float c01 = v01[0] + (v01[1] - v01[0]) * f0;
-                    const float c11 = v11[0] + (v11[1] - v11[0]) * f0;
-                    const float e0 = c00 + (c10 - c00) * f1;
-                    const float e1 = c01 + (c11 - c01) * f1;
-                    v = e0 + (e1 - e0) * f2;
+                    prod *= 1.0f - al;
+                    sa += al;
+                    sr += al * r;
+                    sg += al * gg;
+                    sbl += al * bb;
                 }
-                const ChanLds ch = s_ch[j];
-                float x = (v - ch.w0) * ch.iw;
-                x = fminf(fmaxf(x, 0.0f), 1.0f);
-                const float p = x * 255.0f;
-                int e = (int)p;
-                e = e > 255 ? 255 : e;
-                const int e1i = e < 255 ? e + 1 : 255;
-                const float f = p - (float)e;
-                const float4 ta = s_tf[j * 256 + e], tb = s_tf[j * 256 + e1i];
-                const float al = ta.w + (tb.w - ta.w) * f;
-                const float r = ta.x + (tb.x - ta.x) * f;
-                const float gg = ta.y + (tb.y - ta.y) * f;
-                const float bb = ta.z + (tb.z - ta.z) * f;
-                if constexpr (!HOMOG) ++st_reads;
-                prod *= 1.0f - al;
-                sa += al;
-                sr += al * r;
-                sg += al * gg;
-                sbl += al * bb;
-                if constexpr (!HOMOG) {
-                    if (AOV) A.aov[((size_t)py * A.W + px) * L + (int)((lvpack >> (4 * j)) & 15u)] += 1;
-                }
+                if (AOV && A.aov) A.aov[((size_t)py * A.W + px) * L + (int)((lvpack >> (4 * j)) & 15u)] += 1;
             }
             // the next group's loads are issued after this group is used:
             // bounds the registers held by loads in flight
             asm volatile("" ::: "memory");
         }
+        }
         if (sa > 0.0f) {
-            if (rsh == 0) {
+            if (rsh == 0 || rates) {
                 const float as = 1.0f - prod;
                 const float sc = as / sa;
                 Cr += Tr * (double)(sr * sc);
@@ -957,6 +990,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     stats[3] = st_visits;
     stats[4] = st_nonempty;
     stats[5] = st_iters;
+    stats[6] = st_hom;
 }
 
 // Workgroup set-up: stage the frame's transfer functions, zero-alpha runs,
@@ -964,7 +998,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 // LDS.  Ends with a workgroup barrier.
 template <int NV>
 __device__ __forceinline__ void stage_frame(const RenderArgs &A, float4 *s_tf, ChanLds *s_ch, uint32_t *s_runs,
-                                            LevLds *s_lv, NodeLds *s_nd, uint32_t *s_flat) {
+                                            LevLds *s_lv, NodeLds *s_nd) {
     const int nvis = A.nvis;
     for (int i = threadIdx.x; i < nvis * 256; i += blockDim.x) s_tf[i] = A.tf[i];
     const unsigned t = threadIdx.x;
@@ -976,6 +1010,7 @@ __device__ __forceinline__ void stage_frame(const RenderArgs &A, float4 *s_tf, C
         lv.nbx = A.nbx[t];
         lv.nbxy = A.nbx[t] * A.nby[t];
         lv.K = A.K[t];
+        lv.dd = A.dd[t];
         s_lv[t] = lv;
     }
     if (t >= 64 && t < 64u + (unsigned)A.depth + 1u) {
@@ -999,12 +1034,6 @@ __device__ __forceinline__ void stage_frame(const RenderArgs &A, float4 *s_tf, C
         ch.ehi = (ch.nruns == 1 && (r0 & 0xFFFFu) == 0) ? (r0 >> 16) : 0xFFFFFFFFu;
         ch.single = 0;
         s_ch[t] = ch;
-        if (s_flat) {
-            // word 0 of the channel's block: the run count; the runs follow
-            uint32_t *fl = s_flat + t * (kMaxFlat + 1);
-            fl[0] = (A.flags & RO_RENDER_HOMOGENEOUS) ? (uint32_t)build_flat_runs(s_tf + t * 256, A.W0[t], A.W1[t], fl + 1)
-                                                      : 0u;
-        }
     }
     __syncthreads();
     if (t < (unsigned)nvis) {

@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
             uint32_t *dst = (uint32_t *)&sA;
             for (unsigned i = threadIdx.x; i < sizeof(RenderArgs) / 4; i += blockDim.x) dst[i] = src[i];
             __syncthreads();
-            stage_frame<NV>(sA, s_tf, s_ch, s_runs, s_lv, s_nd, nullptr);
+            stage_frame<NV>(sA, s_tf, s_ch, s_runs, s_lv, s_nd);
             cur = req;
         }
         const uint32_t tiles_x = ((uint32_t)sA.W + 31) / 32, tiles_y = ((uint32_t)sA.H + 31) / 32;
@@ -92,12 +92,12 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
         q.W = sA.W;
         q.H = sA.H;
         q.min_idle = 64;
-        uint32_t st[6] = {0, 0, 0, 0, 0, 0};
+        uint32_t st[7] = {0, 0, 0, 0, 0, 0, 0};
         const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
-        render_rays<NV, BPV, false, EC, true, false>(sA, q, s_tf, s_ch, s_runs, s_lv, s_nd, nullptr, st, sl);
+        render_rays<NV, BPV, false, EC, true, false>(sA, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
         if (sA.stats) {
 #pragma unroll
-            for (int j = 0; j < 6; ++j) {
+            for (int j = 0; j < 7; ++j) {
                 uint32_t v = st[j];
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -311,8 +311,10 @@ extern "C" ro_status ro_serve_prepare(ro_server *s, uint32_t n, const ro_frame_d
     for (uint32_t r = 0; r < n; ++r) {
         ro_status vs = validate_frame(s->tree, &fds[r], rgba[r]);
         if (vs) return vs;
-        RO_CHECK(!(fds[r].flags & RO_RENDER_AOV), RO_E_ARG, "AOV output is not served");
-        RO_CHECK(!(fds[r].flags & RO_RENDER_HOMOGENEOUS), RO_E_ARG, "homogeneous leaves are not served");
+        RO_CHECK(!(fds[r].flags & (RO_RENDER_AOV | RO_RENDER_BRICKS | RO_RENDER_NODES)), RO_E_ARG,
+                 "diagnostic outputs are not served");
+        RO_CHECK(!(fds[r].flags & (RO_RENDER_HOMOGENEOUS | RO_RENDER_CHANNEL_RATES | RO_RENDER_TRAVERSAL_DEPTH)),
+                 RO_E_ARG, "homogeneous nodes, per-channel rates and traversal depths are not served");
         RO_CHECK(fds[r].width <= 65536 && fds[r].height <= 65536, RO_E_ARG, "viewport too large");
         const uint32_t ns = serve_segments(fds[r].width, fds[r].height);
         RO_CHECK(ns <= s->max_tiles - nt, RO_E_CAPACITY, "batch exceeds %u work items", s->max_tiles);

@@ -43,6 +43,12 @@ class GpuScene:
         self.tree.set_leaf_metadata(c, t)
         torch.cuda.current_stream().synchronize()
 
+    def set_unknown(self, c: int):
+        """Every leaf of cache channel c unknown ([0, max raw value]) until
+        brick data give it metadata (Sec. 5.2, Sec. 5.3)."""
+        self.tree.set_leaf_unknown(c)
+        torch.cuda.current_stream().synchronize()
+
     def exchange_channel(self, c: int, src_channel: int, metadata: str = "server"):
         """Run-time channel exchange (Sec. 5.2): cache channel c now holds the
         source's channel src_channel.  The old channel's bricks leave the
@@ -53,11 +59,9 @@ class GpuScene:
         self.cache.evict_channel(c)
         self.channel_map[c] = int(src_channel)
         if metadata == "server":
-            mm = self.src.leaf_minmax(int(src_channel), self.leaf, self.tree.leaf_grid)
+            self.set_metadata(c, self.src.leaf_minmax(int(src_channel), self.leaf, self.tree.leaf_grid))
         else:
-            mm = np.zeros((self.tree.n_leaves, 2), np.uint16)
-            mm[:, 1] = 255 if self.src.bits == 8 else 65535
-        self.set_metadata(c, mm)
+            self.set_unknown(c)
         self.tree.update_residency()
 
     # ------------------------------------------------------------- bricks
@@ -120,13 +124,17 @@ class GpuScene:
         return torch.from_numpy(np.stack([np.asarray(ch["tf"], np.float32) for ch in channels])) \
             .contiguous().to(self.device)
 
-    def render(self, frame, cam, W, H, step, channels, tf_dev=None, out=None, aov=False, **kw):
+    def render(self, frame, cam, W, H, step, channels, tf_dev=None, out=None, aov=False, bricks=False, **kw):
         tf_dev = self.tf_tensor(channels) if tf_dev is None else tf_dev
         out = torch.empty(H * W * 4, dtype=torch.float32, device=self.device) if out is None else out
         aov_t = torch.zeros(H * W * self.vol.n_levels, dtype=torch.int32, device=self.device) if aov else None
-        fd = resoct.frame_desc(frame, cam, W, H, step, channels, tf_dev, self.vol.n_levels, aov=aov_t, **kw)
+        rb_t = torch.empty(H * W * (1 + len(channels)), dtype=torch.int32, device=self.device) if bricks else None
+        fd = resoct.frame_desc(frame, cam, W, H, step, channels, tf_dev, self.vol.n_levels, aov=aov_t,
+                               bricks=rb_t, **kw)
         self.tree.render(fd, out)
         res = {"rgba": out, "fd": fd, "tf": tf_dev}
         if aov:
             res["aov"] = aov_t
+        if bricks:
+            res["bricks"] = rb_t.view(H, W, 1 + len(channels))[..., 0]
         return res

@@ -27,8 +27,10 @@ MAX_CHANNELS = 16
 MAX_LEVELS = 16
 INVALID = 0xFFFFFFFF
 NOALLOC_MAX_PAIRS = 262144  # RO_NOALLOC_MAX_PAIRS
+SNAPSHOT_SLOTS = 1
 PROJ_ORTHO, PROJ_PERSP = 0, 1
-RENDER_NO_SKIP, RENDER_AOV, RENDER_ADAPTIVE_STEP, RENDER_HOMOGENEOUS = 1, 2, 4, 8
+RENDER_NO_SKIP, RENDER_AOV, RENDER_ADAPTIVE_STEP, RENDER_HOMOGENEOUS, RENDER_BRICKS = 1, 2, 4, 8, 16
+RENDER_CHANNEL_RATES, RENDER_NODES, RENDER_TRAVERSAL_DEPTH = 32, 64, 128
 
 c_i32, c_u32, c_u64, c_sz, c_vp, c_dbl = (ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
                                           ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double)
@@ -59,11 +61,12 @@ class OctreeDesc(ctypes.Structure):
 
 class OctreeSizes(ctypes.Structure):
     _fields_ = [("node_meta", c_sz), ("node_mask", c_sz), ("node_flags", c_sz), ("scratch", c_sz),
-                ("n_nodes", c_u64), ("n_leaves", c_u64), ("leaf_grid", c_i32 * 3)]
+                ("leaf_level", c_sz), ("n_nodes", c_u64), ("n_leaves", c_u64), ("leaf_grid", c_i32 * 3)]
 
 
 class OctreeBuffers(ctypes.Structure):
-    _fields_ = [("node_meta", c_vp), ("node_mask", c_vp), ("node_flags", c_vp), ("scratch", c_vp)]
+    _fields_ = [("node_meta", c_vp), ("node_mask", c_vp), ("node_flags", c_vp), ("scratch", c_vp),
+                ("leaf_level", c_vp)]
 
 
 class FrameDesc(ctypes.Structure):
@@ -73,7 +76,8 @@ class FrameDesc(ctypes.Structure):
                 ("n_vis", c_i32), ("vis", c_i32 * MAX_CHANNELS), ("lod_lo", c_i32 * MAX_CHANNELS),
                 ("lod_hi", c_i32 * MAX_CHANNELS), ("win_lo", c_u32 * MAX_CHANNELS),
                 ("win_hi", c_u32 * MAX_CHANNELS), ("tf_dev", c_vp), ("term_alpha", ctypes.c_float),
-                ("start_level", c_i32), ("flags", c_u32), ("aov_dev", c_vp), ("stats_dev", c_vp)]
+                ("start_level", c_i32), ("flags", c_u32), ("aov_dev", c_vp), ("stats_dev", c_vp),
+                ("bricks_dev", c_vp), ("nodes_dev", c_vp)]
 
 
 def _sig(name, res, args):
@@ -108,9 +112,13 @@ _sig("ro_octree_create", c_i32, [c_vp, _P(OctreeDesc), _P(OctreeBuffers), c_vp, 
 _sig("ro_octree_destroy", None, [c_vp])
 _sig("ro_octree_set_leaf_metadata", c_i32, [c_vp, c_u32, c_vp, c_vp])
 _sig("ro_octree_leaf_metadata_from_bricks", c_i32, [c_vp, c_u32, c_vp, c_vp])
+_sig("ro_octree_set_leaf_unknown", c_i32, [c_vp, c_u32, c_vp])
 _sig("ro_update_residency", c_i32, [c_vp, c_vp])
 _sig("ro_rebuild_residency", c_i32, [c_vp, c_vp])
 _sig("ro_render", c_i32, [c_vp, _P(FrameDesc), c_vp, c_vp])
+_sig("ro_snapshot_size", c_i32, [c_vp, c_u32, _P(c_sz)])
+_sig("ro_snapshot", c_i32, [c_vp, c_u32, c_vp, c_sz, _P(c_sz), c_vp])
+_sig("ro_restore", c_i32, [c_vp, c_vp, c_sz, c_vp])
 _sig("ro_mlp_query", c_i32, [_P(c_sz), _P(c_sz)])
 _sig("ro_mlp_create", c_i32, [c_vp, c_vp, _P(c_vp)])
 _sig("ro_mlp_destroy", None, [c_vp])
@@ -302,9 +310,9 @@ class Octree:
         self.sizes = sz
         self.n_nodes, self.n_leaves = int(sz.n_nodes), int(sz.n_leaves)
         self.leaf_grid = tuple(int(x) for x in sz.leaf_grid)
-        self.t = {name: _alloc(getattr(sz, name), device) for name in
-                  ("node_meta", "node_mask", "node_flags", "scratch")}
-        b = OctreeBuffers(*[self.t[n].data_ptr() for n in ("node_meta", "node_mask", "node_flags", "scratch")])
+        names = ("node_meta", "node_mask", "node_flags", "scratch", "leaf_level")
+        self.t = {name: _alloc(getattr(sz, name), device) for name in names}
+        b = OctreeBuffers(*[self.t[n].data_ptr() for n in names])
         h = c_vp()
         _check(_lib.ro_octree_create(cache.h, ctypes.byref(d), ctypes.byref(b), _stream(stream),
                                      ctypes.byref(h)), "ro_octree_create")
@@ -323,11 +331,34 @@ class Octree:
         _check(_lib.ro_octree_set_leaf_metadata(self.h, channel, _dev_ptr(leaf_mm), _stream(stream)),
                "ro_octree_set_leaf_metadata")
 
+    def set_leaf_unknown(self, channel: int, stream=None):
+        _check(_lib.ro_octree_set_leaf_unknown(self.h, channel, _stream(stream)), "ro_octree_set_leaf_unknown")
+
+    def leaf_levels(self) -> np.ndarray:
+        """Metadata level of every leaf and channel, [n_leaves][m] (255 unknown)."""
+        torch.cuda.current_stream().synchronize()
+        m = self.cache.vol.n_channels
+        return self.t["leaf_level"][: self.n_leaves * m].cpu().numpy().reshape(self.n_leaves, m)
+
     def leaf_metadata_from_bricks(self, ids, stream=None):
         ids = np.ascontiguousarray(ids, dtype=np.uint32)
         _check(_lib.ro_octree_leaf_metadata_from_bricks(self.h, len(ids), _np_ptr(ids),
                                                         _stream(stream)),
                "ro_octree_leaf_metadata_from_bricks")
+
+    def snapshot(self, slots: bool = False, stream=None) -> np.ndarray:
+        """ro_snapshot: the octree's and its cache's state as a host blob."""
+        flags = SNAPSHOT_SLOTS if slots else 0
+        n, used = c_sz(), c_sz()
+        _check(_lib.ro_snapshot_size(self.h, flags, ctypes.byref(n)), "ro_snapshot_size")
+        blob = np.empty(n.value, np.uint8)
+        _check(_lib.ro_snapshot(self.h, flags, _np_ptr(blob), n.value, ctypes.byref(used), _stream(stream)),
+               "ro_snapshot")
+        return blob[:used.value]
+
+    def restore(self, blob: np.ndarray, stream=None):
+        blob = np.ascontiguousarray(blob, dtype=np.uint8)
+        _check(_lib.ro_restore(self.h, _np_ptr(blob), blob.size, _stream(stream)), "ro_restore")
 
     def update_residency(self, stream=None):
         _check(_lib.ro_update_residency(self.h, _stream(stream)), "ro_update_residency")
@@ -354,7 +385,8 @@ class Octree:
 
 def frame_desc(frame: int, cam: dict, W: int, H: int, step: float, channels: list, tf_dev: torch.Tensor,
                n_levels: int, term_alpha=0.99, lod_bias=1.0, start_level=-1, flags=0,
-               aov: torch.Tensor = None, stats: torch.Tensor = None):
+               aov: torch.Tensor = None, stats: torch.Tensor = None, bricks: torch.Tensor = None,
+               nodes: torch.Tensor = None):
     """channels: list of {c, lo, hi, W0, W1} in visible-slot order (lo / hi
     default to the full level range); tf_dev is a device float32 tensor
     [n_vis][256][4] in the same order."""
@@ -379,8 +411,13 @@ def frame_desc(frame: int, cam: dict, W: int, H: int, step: float, channels: lis
     fd.tf_dev = tf_dev.data_ptr()
     fd.term_alpha = term_alpha
     fd.start_level = start_level
-    fd.flags = flags | (RENDER_AOV if aov is not None else 0)
+    fd.flags = flags | (RENDER_AOV if aov is not None else 0) | (RENDER_BRICKS if bricks is not None else 0)
     fd.aov_dev = aov.data_ptr() if aov is not None else None
+    if bricks is not None:
+        assert bricks.dtype == torch.int32 and bricks.numel() >= W * H * (1 + len(channels))
+    fd.bricks_dev = bricks.data_ptr() if bricks is not None else None
+    fd.flags |= RENDER_NODES if nodes is not None else 0
+    fd.nodes_dev = nodes.data_ptr() if nodes is not None else None
     fd.stats_dev = stats.data_ptr() if stats is not None else None
     return fd
 

@@ -418,6 +418,62 @@ def window_fx(lo_raw, hi_raw):
 
 # ----------------------------------------------------------------- configs
 
+class ArrayVolume(BlobVolume):
+    """A volume given by its level-0 arrays (one [z][y][x] array per
+    channel); coarser levels by the same 2x box filter as BlobVolume."""
+
+    def __init__(self, arrays, bits=8, spacing=(1, 1, 1), n_levels=3):
+        a0 = [np.ascontiguousarray(a) for a in arrays]
+        nz, ny, nx = a0[0].shape
+        self.dims = (nx, ny, nz)
+        self.spacing = tuple(float(x) for x in spacing)
+        self.n_channels = len(a0)
+        self.bits = bits
+        self.dtype = np.uint8 if bits == 8 else np.uint16
+        self.n_levels = n_levels
+        self.level_dims, self.level_f, halve = level_schedule(self.dims, self.spacing, n_levels)
+        L = lib()
+        self.levels = []
+        for a in a0:
+            assert a.shape == (nz, ny, nx) and a.dtype == self.dtype
+            lv = [a]
+            for l in range(1, n_levels):
+                src = lv[-1]
+                dx, dy, dz = self.level_dims[l]
+                dst = np.empty((dz, dy, dx), dtype=self.dtype)
+                h = halve[l]
+                rc = L.synth_downsample(_ptr(src), bits, src.shape[2], src.shape[1], src.shape[0],
+                                        h[0], h[1], h[2], _ptr(dst))
+                assert rc == 0
+                lv.append(dst)
+            self.levels.append(lv)
+
+
+def plateau_volume(n_channels=2, seed=5, dims=(64, 64, 64), n_levels=3):
+    """u8 volume of constant-valued boxes on a zero background with one
+    Gaussian blob (the only varying data): per channel c, box i holds value
+    v_i + 17 c.  Large parts of it are homogeneous in every channel (the
+    background and box interiors), the blob's leaves in none."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    boxes = []
+    for i in range(4):
+        lo = rng.integers(0, (nx * 3) // 4, 3)
+        ext = rng.integers(nx // 4, nx // 2, 3)
+        boxes.append((lo, lo + ext, int(rng.integers(60, 200))))
+    cen = rng.uniform(0.3, 0.7, 3) * np.array([nx, ny, nz])
+    blob = np.exp(-0.5 * (((x - cen[0]) ** 2 + (y - cen[1]) ** 2 + (z - cen[2]) ** 2) / 5.0 ** 2))
+    out = []
+    for c in range(n_channels):
+        a = np.zeros((nz, ny, nx), np.float64)
+        for lo, hi, v in boxes:
+            a[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = v + 17 * c
+        a = np.maximum(a, np.round(230 * blob))
+        out.append(np.clip(a, 0, 255).astype(np.uint8))
+    return ArrayVolume(out, 8, (1, 1, 1), n_levels)
+
+
 def config1_volume(seed=1):
     """64^3 u8, 40 blobs, noise 0.02, 3 levels."""
     return BlobVolume((64, 64, 64), n_channels=1, bits=8, n_levels=3, seed=seed)

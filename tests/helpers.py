@@ -44,18 +44,38 @@ def gpu_rgba(t, H, W):
     return t.detach().float().cpu().numpy()[: H * W * 4].reshape(H, W, 4).astype(np.float64)
 
 
-def compare_images(gpu, ref, amb_pix, max_abs=1e-3, mean_abs=1e-5, max_amb_frac=1e-3):
+def compare_images(gpu, ref, amb_pix, max_abs=1e-3, mean_abs=1e-5, max_amb_frac=1e-3, alt=None):
     """Per RGBA channel: max abs <= max_abs and mean abs <= mean_abs over the
-    pixels that are not ambiguous; the ambiguous fraction stays small."""
+    pixels that are not ambiguous; the ambiguous fraction stays small.  With
+    alt = (alt_rgba, alt_pix) from the oracle, a pixel whose one termination
+    decision was a close call is compared with whichever of its two valid
+    values it is nearer (by the largest channel difference)."""
     ok = amb_pix == 0
     frac = 1.0 - ok.mean()
-    d = np.abs(gpu - ref)[ok]
+    d = np.abs(gpu - ref)
+    if alt is not None:
+        a_rgba, a_pix = alt
+        da = np.abs(gpu - a_rgba)
+        use = (a_pix != 0) & (da.max(axis=-1) < d.max(axis=-1))
+        d = np.where(use[..., None], da, d)
+    d = d[ok]
     mx = d.max(axis=0) if d.size else np.zeros(4)
     mn = d.mean(axis=0) if d.size else np.zeros(4)
     assert frac <= max_amb_frac, f"ambiguous pixel fraction {frac}"
     assert (mx <= max_abs).all(), f"max abs per channel {mx}"
     assert (mn <= mean_abs).all(), f"mean abs per channel {mn}"
     return dict(max_abs=mx.tolist(), mean_abs=mn.tolist(), amb_frac=frac)
+
+
+def oracle_alt(o):
+    """The (alt_rgba, alt_pix) pair of an oracle frame for compare_images."""
+    return o["alt_rgba"], o["alt_pix"]
+
+
+def aov_mask(o):
+    """Pixels whose per-level read counts are unique: no ambiguous sample and
+    no close termination call (the GPU may take one sample more or less)."""
+    return (o["amb_pix"] == 0) & (o["alt_pix"] == 0)
 
 
 def compare_requests(gpu_ids, gpu_counts, oracle_counts, oracle_amb, dense_ids):

@@ -24,6 +24,6 @@ def test_help_lists_the_measurement_options():
                        timeout=120, cwd=ROOT)
     assert r.returncode == 0
     for opt in ("--gpus", "--steps", "--warmup", "--serve", "--no-prefetch", "--no-streaming", "--no-adaptive",
-                "--no-homogeneous",
+                "--no-homogeneous", "--no-incremental",
                 "--copy-calibration", "--tile"):
         assert opt in r.stdout

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from tests.helpers import compare_images, compare_requests, gpu_rgba
+from tests.helpers import compare_images, compare_requests, gpu_rgba, oracle_alt
 
 pytestmark = pytest.mark.gpu
 
@@ -26,12 +26,10 @@ from tests.test_gpu_render import _report  # noqa: E402
 
 TILE = 128
 # A pixel is ambiguous when a discrete decision of the oracle lies within its
-# margin (positions within 1e-9 of a cell or level boundary, accumulated
-# opacity within 1e-6 of the termination threshold).  With ~700 samples per
-# ray every terminating ray crosses the threshold once, with a per-sample
-# opacity increment around 1e-3, so about 0.1-0.5 % of the window's pixels
-# are ambiguous; they are excluded and bounded here.
-MAX_AMB = 1e-2
+# margin (positions within 1e-9 of a cell or level boundary) or when a ray
+# makes two termination calls within 1e-6 of the threshold; a single close
+# termination call is not ambiguous, the oracle gives both valid outcomes.
+MAX_AMB = 1e-3
 
 
 def test_cfg3_window_parity():
@@ -74,7 +72,8 @@ def _window_parity(f, flags, need, first, name):
     o = oracle.render(V, levels, empty, lm, fr, 1, boxes=boxes)
     assert not np.isnan(o["rgba"]).any()
     n_req = compare_requests(g_ids, g_cnt, o["counts"], o["amb_counts"], ids_all)
-    compare_images(gpu_rgba(r["rgba"], TILE, TILE), o["rgba"], o["amb_pix"], max_amb_frac=MAX_AMB)
+    compare_images(gpu_rgba(r["rgba"], TILE, TILE), o["rgba"], o["amb_pix"], max_amb_frac=MAX_AMB,
+                   alt=oracle_alt(o))
     _report(f"{name}-empty", requests=n_req, missing=tot, samples=o["stats"]["samples"])
 
     # 2. three quarters of the requested bricks resident; for half of the
@@ -103,7 +102,8 @@ def _window_parity(f, flags, need, first, name):
     used_slots, n_used = scene.cache.read_usage(3)
     o = oracle.render(V, levels, res, lm, fr, len(up), boxes=boxes)
     assert not np.isnan(o["rgba"]).any()
-    st = compare_images(gpu_rgba(r["rgba"], TILE, TILE), o["rgba"], o["amb_pix"], max_amb_frac=MAX_AMB)
+    st = compare_images(gpu_rgba(r["rgba"], TILE, TILE), o["rgba"], o["amb_pix"], max_amb_frac=MAX_AMB,
+                   alt=oracle_alt(o))
     n_req = compare_requests(g_ids, g_cnt, o["counts"], o["amb_counts"], ids_all)
     # bricks read: GPU slots mapped through its page table (dense brick
     # order, as the ABI defines it), oracle slots are ranks in `up`

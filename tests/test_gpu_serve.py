@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from tests.helpers import compare_images, gpu_rgba
+from tests.helpers import compare_images, gpu_rgba, oracle_alt
 
 pytestmark = pytest.mark.gpu
 
@@ -177,7 +177,7 @@ def test_served_request_matches_oracle(scene):
     assert r["flags"] & resoct.RENDER_ADAPTIVE_STEP
     fr, keep = oracle.make_frame(r["cam"], r["W"], r["H"], 0.5, r["chans"], term_margin=1e-6, adaptive=True)
     ref = oracle.render(V, src.levels, res_slot, leaf_mm, fr, len(ids))
-    st = compare_images(rig.image(0, o), ref["rgba"], ref["amb_pix"])
+    st = compare_images(rig.image(0, o), ref["rgba"], ref["amb_pix"], alt=oracle_alt(ref))
     _report("serve-oracle", W=r["W"], H=r["H"], channels=len(r["chans"]), **st)
 
 

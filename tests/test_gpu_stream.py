@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from tests.helpers import compare_images, compare_requests, compare_usage, gpu_rgba, leaf_grid
+from tests.helpers import compare_images, compare_requests, compare_usage, gpu_rgba, leaf_grid, oracle_alt
 
 pytestmark = pytest.mark.gpu
 
@@ -17,6 +17,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from tests.test_gpu_render import Pair, _report  # noqa: E402
+from paper_2309_04393_amd import resoct  # noqa: E402
 
 
 def _cells(dims=(512, 512, 64), n_ch=4, n_levels=6, seed=2):
@@ -150,6 +151,61 @@ def test_checkpoint_restore_replays_identically(cells):
             assert np.array_equal(u, v)
 
 
+def test_snapshot_restore_replays_identically(cells):
+    """ro_snapshot / ro_restore: a snapshot with slots taken after frame 2,
+    three more frames of the streaming loop (renders, readbacks, uploads
+    that evict and overwrite slots, residency updates), a restore, and the
+    same three frames again: images, requests and upload flags identical,
+    and the final page table and masks too.  A snapshot without slots
+    restores over frames that upload nothing; blobs of another shape or size
+    are rejected without changing anything."""
+    p = Pair(cells, 32, (16, 16, 4), 5, n_slots=200, max_batch=128)
+    cams = synth.orbit_path(cells.dims, cells.spacing, 6, az_step_deg=12.0)
+    chans = _chans(4)
+    g = p.gpu
+
+    def run(frames, upload=True):
+        outs = []
+        for f in frames:
+            r = g.render(f, cams[f], 64, 64, 0.5, chans)
+            torch.cuda.synchronize()
+            ids, cnt, nu, tot = g.cache.read_requests(1 << 16)
+            fl = np.zeros(0, np.uint8)
+            if upload:
+                fl = g.upload(f, _plain(ids, cnt, 128))
+                g.tree.update_residency()
+            outs.append((r["rgba"].cpu().numpy().copy(), ids.copy(), cnt.copy(), fl.copy()))
+        return outs
+
+    run([1, 2])
+    blob = g.tree.snapshot(slots=True)
+    a = run([3, 4, 5])
+    pt_a, masks_a = g.cache.page_table_host(), g.tree.masks()
+    g.tree.restore(blob)
+    b = run([3, 4, 5])
+    for x, y in zip(a, b):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v)
+    assert np.array_equal(pt_a, g.cache.page_table_host()) and np.array_equal(masks_a, g.tree.masks())
+    # without slots: valid while the slots are untouched (no uploads)
+    small = g.tree.snapshot(slots=False)
+    assert small.size < blob.size
+    c = run([4, 5], upload=False)
+    g.tree.restore(small)
+    d = run([4, 5], upload=False)
+    for x, y in zip(c, d):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v)
+    # a truncated blob and one from another cache are rejected; state unchanged
+    with pytest.raises(resoct.ResoctError):
+        g.tree.restore(small[:-4])
+    other = Pair(cells, 32, (16, 16, 4), 5, n_slots=100, max_batch=128)
+    with pytest.raises(resoct.ResoctError):
+        g.tree.restore(other.gpu.tree.snapshot())
+    e = run([4], upload=False)
+    assert np.array_equal(e[0][0], d[0][0])
+
+
 def test_run_is_deterministic(cells):
     """Determinism is the race test: the same frame twice gives identical
     counters, stamps, masks and page tables."""
@@ -210,7 +266,7 @@ def test_leaf_metadata_from_bricks(cells):
     unknown = np.zeros((cells.n_channels, n_leaves, 2), np.uint16)
     unknown[..., 1] = 65535
     for c in range(cells.n_channels):
-        p.gpu.set_metadata(c, unknown[c])
+        p.gpu.set_unknown(c)
     _, _, nb = oracle.level_info(p.V)
     l0 = [oracle.brick_id(p.V.n_levels, c, 0, x, y, 0) for c in (0, 2) for y in range(nb[0][1])
           for x in range(min(8, nb[0][0]))]
@@ -275,7 +331,7 @@ def test_channel_exchange():
         mm = np.stack([src.leaf_minmax(s, leaf, lg) for s in g.channel_map])
         o = oracle.render(V, levels, sim.res_slot, mm, fr, S)
         sim.touch(f, o["used"])
-        st = compare_images(gpu_rgba(r["rgba"], 72, 72), o["rgba"], o["amb_pix"])
+        st = compare_images(gpu_rgba(r["rgba"], 72, 72), o["rgba"], o["amb_pix"], alt=oracle_alt(o))
         compare_requests(ids, cnt, o["counts"], o["amb_counts"], dense)
         compare_usage(used, o["used"], o["amb_used"])
         _report(name, requests=nu, **st)
@@ -307,13 +363,15 @@ def test_leaf_metadata_from_u8_bricks():
     """The u8 path of the metadata-from-bricks kernel: from every level-0
     brick of the 64^3 blob volume the derived metadata equal the oracle's and
     the data server's exact leaf metadata (L0 values within one voxel of the
-    leaf); then level-1 bricks alone give the oracle's coarse estimate."""
+    leaf); then level-1 bricks alone give the oracle's coarse estimate; level
+    0 then level 1 again: the level-1 call leaves the exact metadata (finer
+    data are never replaced by coarser)."""
     src = synth.config1_volume()
     p = Pair(src, 16, (8, 8, 8), 3, n_slots=73)
     n_leaves = p.leaf_mm.shape[1]
     unknown = np.zeros((1, n_leaves, 2), np.uint16)
     unknown[..., 1] = 255
-    p.gpu.set_metadata(0, unknown[0])
+    p.gpu.set_unknown(0)
     ids = p.gpu.all_ids()
     p.upload(0, ids)
     l0 = [int(i) for i in p.gpu.all_ids(levels=[0])]
@@ -322,9 +380,62 @@ def test_leaf_metadata_from_u8_bricks():
     ref = oracle.leaf_meta_from_bricks(p.V, src.levels, unknown, l0)
     assert np.array_equal(ref, p.leaf_mm)  # the server's exact metadata
     assert np.array_equal(p.gpu.tree.meta(), oracle.meta_all(p.V, ref))
-    p.gpu.set_metadata(0, unknown[0])
+    p.gpu.set_unknown(0)
     l1 = [int(i) for i in p.gpu.all_ids(levels=[1])]
     p.gpu.tree.leaf_metadata_from_bricks(np.array(l1, np.uint32))
     torch.cuda.synchronize()
     ref1 = oracle.leaf_meta_from_bricks(p.V, src.levels, unknown, l1)
     assert np.array_equal(p.gpu.tree.meta(), oracle.meta_all(p.V, ref1))
+    assert (p.gpu.tree.leaf_levels() == 1).all()
+    for ids_ in (l0, l1):
+        p.gpu.tree.leaf_metadata_from_bricks(np.array(ids_, np.uint32))
+    torch.cuda.synchronize()
+    assert np.array_equal(p.gpu.tree.meta(), oracle.meta_all(p.V, ref))
+    assert (p.gpu.tree.leaf_levels() == 0).all()
+
+
+def test_incremental_metadata_loop(cells):
+    """Alg. 1 reportNodeRequest / Sec. 5.3 without server metadata: every
+    leaf starts unknown; each frame renders, the plain policy uploads the
+    requested bricks, and the inserted bricks give their leaves metadata
+    (finer data refine, coarser never replace).  Every frame's image,
+    requests and usage, the node metadata, the leaves' metadata levels and
+    the masks match an oracle running the same loop; the same view rendered
+    again at the end evaluates fewer samples (skipping has switched on where
+    the data showed empty space)."""
+    p = Pair(cells, 32, (16, 16, 4), 5, n_slots=600, max_batch=256)
+    g = p.gpu
+    n_leaves = p.leaf_mm.shape[1]
+    for c in range(cells.n_channels):
+        g.set_unknown(c)
+    mm = np.zeros((cells.n_channels, n_leaves, 2), np.uint16)
+    mm[..., 1] = 65535
+    lvl = np.full((cells.n_channels, n_leaves), 255, np.uint8)
+    p.leaf_mm = mm
+    assert np.array_equal(g.tree.meta(), oracle.meta_all(p.V, mm))
+    cams = synth.orbit_path(cells.dims, cells.spacing, 8, az_step_deg=10.0)
+    chans = _chans(4)
+    st0 = torch.zeros(8, dtype=torch.int64, device="cuda")
+    first = None
+    for f in range(1, 7):
+        st = torch.zeros(8, dtype=torch.int64, device="cuda")
+        res = p.frame(f, cams[f], 80, 80, 0.5, chans, lod_bias=0.8, stats=st)
+        p.check_frame(res, f"incremental-{f}")
+        if f == 1:
+            first = int(st[0].item())
+        up = _plain(res["ids"], res["cnt"], 256)
+        flags = p.upload(f, up)
+        got = up[flags == 1]
+        g.tree.leaf_metadata_from_bricks(got)
+        p.leaf_mm, lvl = oracle.leaf_meta_from_bricks(p.V, cells.levels, p.leaf_mm, got, lvl)
+        torch.cuda.synchronize()
+        want = oracle.meta_all(p.V, p.leaf_mm)
+        have = g.tree.meta()
+        assert np.array_equal(have, want), f"frame {f}: metadata differ at {np.argwhere(have != want)[:5]}"
+        assert np.array_equal(g.tree.leaf_levels().T, lvl), f"frame {f}: metadata levels differ"
+        p.check_masks()
+    known = (lvl < 255).mean()
+    res = p.frame(7, cams[1], 80, 80, 0.5, chans, lod_bias=0.8, stats=st0)
+    p.check_frame(res, "incremental-again")
+    _report("incremental", known_leaf_fraction=float(known), samples_first=first, samples_again=int(st0[0].item()))
+    assert known > 0.1 and int(st0[0].item()) < first

@@ -116,3 +116,34 @@ def test_coarse_estimate_is_within_the_fine_range_for_averaged_levels():
               for ax, i in enumerate((lx, ly, lz))]
         sub = a[sl[2], sl[1], sl[0]]
         assert sub.min() <= l1[k, 0] <= l1[k, 1] <= sub.max()
+
+
+def test_metadata_levels_across_calls_equal_one_call():
+    """With the per-leaf metadata level, splitting the bricks over calls in
+    any order (finest first, coarsest first, interleaved) gives the result
+    of one call over all of them (finest wins), and each leaf's level is the
+    finest level of a brick covering it (255 where none does).  Without the
+    levels a later coarser call would overwrite finer metadata."""
+    V, levels, unknown, ng, d, f, nb = _scene(seed=5)
+    fine = _ids(V, 0, 0, nb)[::3] + _ids(V, 1, 0, nb)[:4]
+    mid = _ids(V, 0, 1, nb)[::2]
+    coarse = _ids(V, 0, 2, nb) + _ids(V, 1, 2, nb)
+    lvl0 = np.full(unknown.shape[:2], 255, np.uint8)
+    one, one_lvl = oracle.leaf_meta_from_bricks(V, levels, unknown, fine + mid + coarse, lvl0)
+    assert np.array_equal(one, oracle.leaf_meta_from_bricks(V, levels, unknown, fine + mid + coarse))
+    for parts in ((fine, mid, coarse), (coarse, mid, fine), (mid, fine, coarse), (coarse, fine, mid)):
+        mm, lv = unknown, lvl0
+        for p in parts:
+            mm, lv = oracle.leaf_meta_from_bricks(V, levels, mm, p, lv)
+        assert np.array_equal(mm, one) and np.array_equal(lv, one_lvl)
+    # the levels are the finest covering brick's
+    for ids, l in ((coarse, 2), (mid, 1), (fine, 0)):
+        _, lv = oracle.leaf_meta_from_bricks(V, levels, unknown, ids, lvl0)
+        assert set(np.unique(lv)) <= {l, 255} and (lv == l).any()
+    # a coarser call after a finer one changes nothing where the finer one reached
+    mm_f, lv_f = oracle.leaf_meta_from_bricks(V, levels, unknown, fine, lvl0)
+    mm_fc, lv_fc = oracle.leaf_meta_from_bricks(V, levels, mm_f, coarse, lv_f)
+    hit = lv_f == 0
+    assert hit.any() and np.array_equal(mm_fc[hit], mm_f[hit]) and (lv_fc[hit] == 0).all()
+    plain = oracle.leaf_meta_from_bricks(V, levels, mm_f, coarse)
+    assert not np.array_equal(plain[hit], mm_f[hit])  # what the levels prevent

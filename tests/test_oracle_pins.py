@@ -179,6 +179,39 @@ def test_constant_volume_closed_form(a):
     assert (r["aov"][..., 0] == n).all()
 
 
+@pytest.mark.parametrize("side", [-1, 0, 1])
+def test_close_termination_call_has_both_outcomes(side):
+    """Early termination (A >= alpha_term after a sample) decided within the
+    margin of alpha_term: both outcomes are valid images, so the pixel is not
+    ambiguous; the oracle keeps the other one.  Constant alpha a: after n
+    samples A_n = 1 - (1-a)^n.  With alpha_term at A_8 (side 0) or just
+    below it (side -1) this oracle stops after 8 samples and the other
+    outcome is one more sample, A_9; just above it (side +1) it stops after 9
+    and the other outcome is A_8.  Colours are rgb * A."""
+    a = 0.2
+    af = float(np.float32(a))
+    vol = np.full((16, 16, 16), 128, np.uint8)
+    tf = _const_tf((0.2, 0.4, 0.6), a)
+    ch = [dict(c=0, lo=0, hi=0, W0=0, W1=255 * 256, tf=tf)]
+    V = _scene_V([[vol]], 8, 8, (4, 4, 4), 2)
+    cam = synth.camera_ortho_axis((16, 16), 16, 16)
+    A8, A9 = 1 - (1 - af) ** 8, 1 - (1 - af) ** 9
+    term = float(np.nextafter(A8, 2.0 * side)) if side else A8
+    fr, keep = oracle.make_frame(cam, 16, 16, 0.5, ch, term_alpha=0.99, term_margin=1e-6)
+    fr.term_alpha = term
+    r = oracle.render(V, [[vol]], _all_resident(V), _leaf_mm_full(V, [[vol]]), fr, oracle.brick_count(V))
+    first, other = (A9, A8) if side > 0 else (A8, A9)
+    rgb = np.array([np.float32(0.2), np.float32(0.4), np.float32(0.6)], dtype=np.float64)
+    assert (r["amb_pix"] == 0).all() and (r["alt_pix"] == 1).all()
+    assert np.allclose(r["rgba"][..., 3], first, atol=1e-12, rtol=0)
+    assert np.allclose(r["alt_rgba"][..., 3], other, atol=1e-12, rtol=0)
+    assert np.allclose(r["alt_rgba"][..., :3], rgb * other, atol=1e-12, rtol=0)
+    # far from the threshold there is one outcome
+    fr.term_alpha = 0.5 * (A8 + A9)
+    r = oracle.render(V, [[vol]], _all_resident(V), _leaf_mm_full(V, [[vol]]), fr, oracle.brick_count(V))
+    assert (r["alt_pix"] == 0).all() and np.allclose(r["rgba"][..., 3], A9, atol=1e-12, rtol=0)
+
+
 @pytest.mark.parametrize("a", [0.05, 0.2, 0.5])
 def test_adaptive_step_constant_volume_closed_form(a):
     """LOD-adaptive step (Sec. 6.1: the sampling distance may grow with the
@@ -803,3 +836,175 @@ def test_paper_scale_metadata_is_conservative():
         checked += reg[0].size
         n_empty_checked += int((bound == 0).sum())
     assert checked.min() >= 10 ** 6 and n_empty_checked >= 16 * 50
+
+
+# ------------------------------------------------ bricks required per pixel
+
+@pytest.mark.parametrize("level,n_ch", [(0, 1), (1, 1), (0, 2), (2, 2)])
+def test_required_bricks_axis_closed_form(level, n_ch):
+    """Sec. 8 (bricks required to be resident per pixel): an axis ray through
+    a 64^3 volume with nothing empty and no early termination needs, per
+    channel, the level-l bricks of edge 16 f_l it crosses in z: 64 / (16 f_l),
+    whatever is resident (the count is of desired bricks)."""
+    vol = np.full((64, 64, 64), 100, np.uint8)
+    levels = [[vol, vol[::2, ::2, ::2].copy(), vol[::4, ::4, ::4].copy()] for _ in range(n_ch)]
+    V = _scene_V(levels, 8, 16, (8, 8, 8), 3)
+    chans = [dict(c=c, lo=level, hi=level, W0=0, W1=255 * 256, tf=_const_tf((0.5, 0.5, 0.5), 1e-4))
+             for c in range(n_ch)]
+    cam = synth.camera_ortho_axis((64, 64), 32, 32)
+    fr, keep = oracle.make_frame(cam, 32, 32, 0.5, chans)
+    for res in (_all_resident(V), np.full(oracle.brick_count(V), -1, np.int32)):
+        r = oracle.render(V, levels, res, _leaf_mm_full(V, levels), fr, oracle.brick_count(V))
+        assert (r["required_bricks"] == n_ch * (64 // (16 << level))).all()
+
+
+@pytest.mark.parametrize("seed,homog", [(0, False), (1, False), (2, True), (3, True)])
+def test_required_bricks_equal_the_pixel_read_set(seed, homog):
+    """With every level-0 brick resident and level 0 desired, the bricks a
+    pixel requires are the bricks it reads: for one-pixel frames on random
+    views, the count equals the number of slots the frame marks as read
+    (a separate output: the usage set), with empty leaves, early termination
+    and, with the option on, nodes rendered from their values (which read
+    and require nothing)."""
+    rng = np.random.default_rng(seed)
+    if homog:
+        src = synth.plateau_volume(2)
+        leaf, depth = (4, 4, 4), 4
+        chans = []
+        for c in range(2):
+            tf = synth.tf_hue(c / 2, 0.3)
+            tf[:, 3] = np.maximum(tf[:, 3], np.float32(0.004))
+            chans.append(dict(c=c, lo=0, hi=0, W0=0, W1=255 * 256, tf=tf))
+    else:
+        src = synth.config1_volume()
+        leaf, depth = (8, 8, 8), 3
+        W0, W1 = synth.window_fx(0.05 * 255, 255)
+        chans = [dict(c=0, lo=0, hi=0, W0=W0, W1=W1, tf=synth.tf_ramp())]
+    V = oracle.make_volume(src.dims, src.spacing, src.n_channels, src.bits, 16, src.n_levels, leaf, depth)
+    lg = leaf_grid(src.dims, leaf, depth)
+    lm = np.stack([src.leaf_minmax(c, leaf, lg) for c in range(src.n_channels)])
+    full = _all_resident(V)
+    hits = 0
+    for _ in range(12):
+        eye = rng.uniform(-40, 104, 3)
+        eye[rng.integers(0, 3)] = rng.choice([-60.0, 124.0])
+        tgt = rng.uniform(16, 48, 3)
+        cam = synth.camera_persp(eye, tgt, (0, 0, 1) if abs(eye[2] - tgt[2]) < 50 else (1, 0, 0), 1.0, 1.0)
+        fr, keep = oracle.make_frame(cam, 1, 1, 0.5, chans, homogeneous=homog)
+        r = oracle.render(V, src.levels, full, lm, fr, oracle.brick_count(V))
+        assert r["required_bricks"][0, 0] == r["used"].sum()
+        hits += r["used"].sum() > 1
+    assert hits >= 6
+
+
+# ------------------------------------------- per-channel sampling rates (f1)
+
+def _two_const(a0, a1, rgb0=(0.2, 0.4, 0.6), rgb1=(0.2, 0.4, 0.6)):
+    l = [np.full((16 >> i, 16 >> i, 16 >> i), 128, np.uint8) for i in range(3)]
+    levels = [l, [x.copy() for x in l]]
+    V = _scene_V(levels, 8, 8, (4, 4, 4), 2)
+    chans = [dict(c=0, lo=0, hi=0, W0=0, W1=255 * 256, tf=_const_tf(rgb0, a0)),
+             dict(c=1, lo=1, hi=1, W0=0, W1=255 * 256, tf=_const_tf(rgb1, a1))]
+    return levels, V, chans
+
+
+@pytest.mark.parametrize("a0,a1", [(0.01, 0.02), (0.0, 0.05), (0.03, 0.0)])
+def test_channel_rates_two_constant_channels(a0, a1):
+    """Sec. 6.1 (a channel may need only every second step): channel 0 at
+    level 0 (rate 1), channel 1 at level 1 (rate 2, x factor 2).  An axis ray
+    has 32 base samples in [0, 16); channel 1 takes part in the 16 even ones,
+    each standing for two steps, so the opacity keeps its value per unit
+    length: A = 1 - (1-a0)^32 (1-a1)^32 (equal colours: C = rgb A), and with
+    nothing resident channel 0 requests 32 times per ray, channel 1 16 times
+    (at its level 1)."""
+    levels, V, chans = _two_const(a0, a1)
+    cam = synth.camera_ortho_axis((16, 16), 16, 16)
+    fr, keep = oracle.make_frame(cam, 16, 16, 0.5, chans, adaptive=True, channel_rates=True)
+    r = oracle.render(V, levels, _all_resident(V), _leaf_mm_full(V, levels), fr, oracle.brick_count(V))
+    f0, f1 = float(np.float32(a0)), float(np.float32(a1))
+    A = 1 - (1 - f0) ** 32 * (1 - f1) ** 32
+    rgb = np.array([np.float32(0.2), np.float32(0.4), np.float32(0.6)], dtype=np.float64)
+    assert np.allclose(r["rgba"][..., 3], A, atol=1e-12, rtol=0)
+    assert np.allclose(r["rgba"][..., :3], rgb * A, atol=1e-12, rtol=0)
+    none = np.full(oracle.brick_count(V), -1, np.int32)
+    r = oracle.render(V, levels, none, _leaf_mm_full(V, levels), fr, 1)
+    ids = oracle.dense_ids(V)
+    per = {0: 0, 1: 0}
+    for i in np.nonzero(r["counts"])[0]:
+        c, l, _, _, _ = oracle.brick_id_decode(V.n_levels, int(ids[i]))
+        assert l == (0 if c == 0 else 1)
+        per[c] += int(r["counts"][i])
+    # a channel whose table has zero alpha everywhere is empty: it requests nothing
+    assert per[0] == (16 * 16 * 32 if a0 > 0 else 0)
+    assert per[1] == (16 * 16 * 16 if a1 > 0 else 0)
+
+
+def test_channel_rates_reduce_to_the_adaptive_step():
+    """With every channel at one level range the rates coincide with the
+    step's, so the option changes nothing (images within FP64 rounding, the
+    same requests and reads), on oblique views over the blob volume with
+    part of the bricks resident."""
+    src = synth.config1_volume()
+    V = oracle.make_volume(src.dims, src.spacing, 1, 8, 16, src.n_levels, (8, 8, 8), 3)
+    lm = src.leaf_minmax(0, (8, 8, 8), leaf_grid(src.dims, (8, 8, 8), 3))[None]
+    W0, W1 = synth.window_fx(0.05 * 255, 255)
+    chans = [dict(c=0, lo=0, hi=2, W0=W0, W1=W1, tf=synth.tf_ramp())]
+    rng = np.random.default_rng(2)
+    res = np.full(oracle.brick_count(V), -1, np.int32)
+    pick = np.nonzero(rng.random(oracle.brick_count(V)) < 0.6)[0]
+    res[pick] = np.arange(len(pick))
+    cam = synth.camera_persp((120.0, 95.0, 80.0), (32, 30, 34), (0, 0, 1), 50.0, 1.25)
+    out = []
+    for rates in (False, True):
+        fr, keep = oracle.make_frame(cam, 48, 40, 0.5, chans, lod_bias=1.5, adaptive=True, channel_rates=rates)
+        out.append(oracle.render(V, src.levels, res, lm, fr, len(pick)))
+    p, q = out
+    assert np.abs(p["rgba"] - q["rgba"]).max() < 1e-12
+    assert np.array_equal(p["counts"], q["counts"]) and np.array_equal(p["used"], q["used"])
+    assert p["stats"]["samples"] > 0 and p["rgba"][..., 3].max() > 0.01
+
+
+# --------------------------------------------- traversal depth from the step (f1)
+
+def test_traversal_depth_equals_a_coarser_tree():
+    """Alg. 1 chooseTraversalDepth: with samples 5 world units apart (step
+    2.5, level 1 so r = 2) and 4^3 leaves, the deepest node whose extent is
+    at least the step is the 8^3 node one level up; emptiness decided there
+    equals rendering a tree whose leaves are 8^3, with the metadata of those
+    nodes (min and max over their 4^3 leaves, which is also the exact dilated
+    metadata of the 8^3 box), without the option: images, requests and reads
+    identical.  Without the option the finer leaves decide and fewer samples
+    read data (so the pin is not vacuous); with a step of 0.5 the leaf is
+    deep enough and the option changes nothing."""
+    src = synth.config1_volume()
+    W0, W1 = synth.window_fx(0.05 * 255, 255)
+    chans = [dict(c=0, lo=0, hi=2, W0=W0, W1=W1, tf=synth.tf_ramp())]
+    VA = oracle.make_volume(src.dims, src.spacing, 1, 8, 16, src.n_levels, (4, 4, 4), 4)
+    VB = oracle.make_volume(src.dims, src.spacing, 1, 8, 16, src.n_levels, (8, 8, 8), 3)
+    lmA = src.leaf_minmax(0, (4, 4, 4), leaf_grid(src.dims, (4, 4, 4), 4))[None]
+    lmB = src.leaf_minmax(0, (8, 8, 8), leaf_grid(src.dims, (8, 8, 8), 3))[None]
+    nodesA = oracle.meta_all(VA, lmA)  # [node][c][2]
+    _, offA, _ = oracle.node_count(VA)
+    assert np.array_equal(nodesA[offA[3]:offA[4], 0], lmB[0])
+    full = np.arange(oracle.brick_count(VA), dtype=np.int32)
+    res = full.copy()
+    res[np.random.default_rng(1).random(len(res)) < 0.3] = -1
+    cam = synth.camera_oblique_ortho((64, 64, 64), (1, 1, 1), 3, 64, 64)
+    for r_ in (full, res):
+        fa, ka = oracle.make_frame(cam, 64, 64, 2.5, chans, lod_bias=1.5, adaptive=True, traversal_depth=True)
+        fb, kb = oracle.make_frame(cam, 64, 64, 2.5, chans, lod_bias=1.5, adaptive=True)
+        a = oracle.render(VA, src.levels, r_, lmA, fa, len(full), aov=True)
+        b = oracle.render(VB, src.levels, r_, lmB, fb, len(full), aov=True)
+        c = oracle.render(VA, src.levels, r_, lmA, fb, len(full), aov=True)
+        # every sample desires level 1 (level 2 only substitutes for missing level-1 bricks)
+        assert (a["aov"][..., 1] > 0).any() and a["aov"][..., 0].sum() == 0
+        assert r_ is res or a["aov"][..., 2].sum() == 0
+        assert np.array_equal(a["rgba"], b["rgba"])
+        assert np.array_equal(a["counts"], b["counts"]) and np.array_equal(a["used"], b["used"])
+        # without the option the 4^3 leaves decide: fewer samples read data
+        assert c["stats"]["channel_samples"] < a["stats"]["channel_samples"]
+    fa, ka = oracle.make_frame(cam, 64, 64, 0.5, chans, lod_bias=1.5, adaptive=True, traversal_depth=True)
+    fc, kc = oracle.make_frame(cam, 64, 64, 0.5, chans, lod_bias=1.5, adaptive=True)
+    a = oracle.render(VA, src.levels, full, lmA, fa, len(full))
+    c = oracle.render(VA, src.levels, full, lmA, fc, len(full))
+    assert np.array_equal(a["rgba"], c["rgba"]) and np.array_equal(a["counts"], c["counts"])
