@@ -47,7 +47,6 @@ def profiled_traffic(workload):
     this workload (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known
     size), or None when the summary is missing or the kernel's sources have
     changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"k_render-{workload}.md")
     if not os.path.exists(path):
         return None
@@ -56,16 +55,68 @@ def profiled_traffic(workload):
         return None
     block = txt.split("<!-- roofline", 1)[1].split("-->", 1)[0]
     kv = dict(line.split(": ", 1) for line in block.strip().splitlines() if ": " in line)
-    h = hashlib.sha256()
-    for f in ("render_core.h", "render.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2309_04393_amd", "csrc", f), "rb").read())
-    if kv.get("kernel_sources_sha256") != h.hexdigest() or kv.get("workload") != workload:
+    if kv.get("kernel_sources_sha256") != kernel_sources_sha256() or kv.get("workload") != workload:
         return None
     return float(kv["traffic_bytes_per_launch"])
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("render_core.h", "render.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2309_04393_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(path, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def profile_summary(trace_dir, fetch_dir, write_dir, last, workload, kernel="k_render<16, 2, false, 34, false>"):
+    """Markdown summary of rocprofv3 runs of the headline frame loop: mean
+    duration of the last `last` dispatches of the headline kernel (the timed
+    pass; the untimed pass A and the warm-up frames come before it) from the
+    kernel trace, and FETCH_SIZE / WRITE_SIZE of the same dispatches, scaled by
+    what the counters read for the 1 GiB device copy (--copy-calibration)."""
+    tr = [r for r in _csv_rows(trace_dir, "kernel_trace.csv") if kernel in r["Kernel_Name"]]
+    tr.sort(key=lambda r: int(r["Dispatch_Id"]))
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in tr]
+    sel = dur[-last:]
+
+    def counter(d, name):
+        rows = _csv_rows(d, "counter_collection.csv")
+        k = sorted((r for r in rows if kernel in r["Kernel_Name"] and r["Counter_Name"].startswith(name)),
+                   key=lambda r: int(r["Dispatch_Id"]))
+        cp = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
+              and r["Counter_Name"].startswith(name)]
+        return [float(r["Counter_Value"]) for r in k][-last:], (max(cp) if cp else None)
+
+    fetch, fcopy = counter(fetch_dir, "FETCH_SIZE")
+    write, wcopy = counter(write_dir, "WRITE_SIZE")
+    gib_kib = (1 << 30) / 1024.0
+    fs = gib_kib / fcopy if fcopy else 1.0
+    ws = gib_kib / wcopy if wcopy else 1.0
+    traffic = (np.mean(fetch) * fs + np.mean(write) * ws) * 1024.0
+    mean_ms = float(np.mean(sel))
+    lines = [f"* `{kernel}`: {len(tr)} dispatches; the last {len(sel)} (the timed pass): mean {mean_ms:.3f} ms, "
+             f"min {min(sel):.3f}, max {max(sel):.3f}.",
+             f"* Copy calibration: FETCH_SIZE {fcopy} KiB and WRITE_SIZE {wcopy} KiB for a 1 GiB copy; factors "
+             f"{fs:.4f} and {ws:.4f}.",
+             f"* Per timed launch: FETCH_SIZE {np.mean(fetch):.4g} KiB, WRITE_SIZE {np.mean(write):.4g} KiB -> "
+             f"{traffic / 1e9:.2f} GB = {traffic / 1e9 / (mean_ms / 1e3):.0f} GB/s of fabric traffic.",
+             "", "<!-- roofline", f"workload: {workload}", f"kernel_sources_sha256: {kernel_sources_sha256()}",
+             f"mean_ms_timed_launches: {mean_ms:.4f}", f"traffic_bytes_per_launch: {traffic:.0f}", "-->"]
+    return "\n".join(lines)
 
 
 def config(name):
@@ -434,9 +485,11 @@ def adaptive_bench(scene, fl, frames, reps=3):
                              lane_busy=float(st[0]) / max(float(st[5]), 1.0))
         row["speedup"] = row["plain"]["ms"] / row["adaptive"]["ms"]
         # per-channel sampling rates (Sec. 6.1) with mixed per-channel level
-        # ranges (Sec. 6.2, Fig. 6): channel c at levels >= c mod 4; the mixed
-        # frame's working set is made resident first
-        mixed = [dict(ch, lo=min(c % 4, ch["hi"])) for c, ch in enumerate(fl.chans)]
+        # ranges (Sec. 6.2, Fig. 6): channel c at levels >= 2 (c mod 4), a
+        # quarter of the channels at full resolution and the others two,
+        # four and six levels coarser; the mixed frame's working set is made
+        # resident first
+        mixed = [dict(ch, lo=min(2 * (c % 4), ch["hi"])) for c, ch in enumerate(fl.chans)]
         for it in range(3):
             scene.render(f, fl.cams[f], fl.W, fl.H, fl.step, mixed, tf_dev=fl.tf, out=fl.out,
                          flags=resoct.RENDER_ADAPTIVE_STEP)
@@ -654,11 +707,13 @@ def incremental_bench(n_frames=16, W=768, H=768, U=512):
     """Incremental metadata (Alg. 1 reportNodeRequest, Sec. 5.3 without
     server metadata) on the 4-channel 2048x2048x64 cell volume, orbit path
     from a cold cache: the request-driven loop (render, plain policy, upload,
-    residency update) once with every leaf unknown and refined from the
-    inserted bricks, once with the server's metadata.  Per frame: kernel time
-    from HIP events, ray samples evaluated, samples skipped as empty space
-    (the base-step positions a lane skips), and the share of leaves with
-    metadata."""
+    residency update) with every leaf unknown and refined from the inserted
+    bricks ("refined"), with every leaf unknown and never refined ("never":
+    no empty space is ever skipped), and with the server's metadata
+    ("server").  Per frame: kernel time from HIP events, ray samples
+    evaluated, missing samples, uploads and the share of leaves with
+    metadata; and the largest difference of the last frame's image from the
+    server run's (metadata from coarse bricks are estimates, R32)."""
     import torch
     import synth
     from paper_2309_04393_amd.pipeline import GpuScene
@@ -667,10 +722,11 @@ def incremental_bench(n_frames=16, W=768, H=768, U=512):
     chans = [dict(ch, hi=vol.n_levels - 1) for ch in channels(vol.n_channels, 2)]
     out = {"workload": "4ch-2048x2048x64-u16 orbit, cold 27318-slot cache", "image": [W, H],
            "upload_budget": U, "frames": n_frames}
-    for mode in ("unknown", "server"):
+    last = {}
+    for mode in ("refined", "never", "server"):
         scene = GpuScene(vol, 32, (16, 16, 4), 7, 27318, max_batch=U, start_level=2,
                          set_metadata=(mode == "server"))
-        if mode == "unknown":
+        if mode != "server":
             for c in range(vol.n_channels):
                 scene.set_unknown(c)
         tf = scene.tf_tensor(chans)
@@ -689,19 +745,24 @@ def incremental_bench(n_frames=16, W=768, H=768, U=512):
             up = ids[order][:U]
             if len(up):
                 flags = scene.upload(f + 1, up)
-                if mode == "unknown":
+                if mode == "refined":
                     scene.tree.leaf_metadata_from_bricks(up[flags == 1])
             scene.tree.update_residency()
             torch.cuda.synchronize()
             st = stats.cpu().numpy()
             row = dict(ms=a.elapsed_time(b), samples=int(st[0]), missing=int(tot), uploads=int(len(up)))
-            if mode == "unknown":
-                row["known_leaves"] = float((scene.tree.leaf_levels() < 255).mean())
+            if mode != "server":
+                lv = scene.tree.leaf_levels()
+                row["known_leaves"] = float((lv < 255).mean())
+                row["level0_leaves"] = float((lv == 0).mean())
             rows.append(row)
         out[mode] = rows
+        last[mode] = img.cpu().numpy()
         log(f"incremental metadata ({mode}): " + ", ".join(f"{r['ms']:.2f}" for r in rows) + " ms")
         del scene
         torch.cuda.empty_cache()
+    for mode in ("refined", "never"):
+        out[f"{mode}_last_frame_max_abs_diff_from_server"] = float(np.abs(last[mode] - last["server"]).max())
     return out
 
 
@@ -803,10 +864,15 @@ def main():
     ap.add_argument("--pf-steps", type=int, default=4, help="Adam steps per frame")
     ap.add_argument("--pf-threshold", type=float, default=0.5, help="candidate probability threshold")
     ap.add_argument("--pf-gate", type=float, default=0.5, help="precision below which the plain policy is used")
+    ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="print the summary of rocprofv3 output directories of the headline loop (no GPU work)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the measurement, copy a 1 GiB buffer three times (a plain copy kernel of "
                          "known size, to scale hardware byte counters)")
     args = ap.parse_args()
+    if args.profile_summary:
+        print(profile_summary(*args.profile_summary, last=args.steps, workload=config(args.config)["name"]))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not implemented",
                           "n_gpus": args.gpus}))

@@ -355,17 +355,28 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const _Float16 *__restrict__ x
     }
 }
 
-// Sum the partials in a fixed order; grad = sum / mask count.
-__global__ void k_mlp_reduce(const float *__restrict__ part, int nparts, float *__restrict__ grad,
-                             float *__restrict__ stat) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= kNP + kStat) return;
-    float s = 0.0f;
-    for (int w = 0; w < nparts; ++w) s += part[(size_t)w * (kNP + kStat) + k];
-    if (k < kNP) {
-        grad[k] = s;
-    } else {
-        stat[k - kNP] = s;
+// Sum the partials in a fixed order (deterministic): a block takes 64
+// parameters; each of its 16 waves sums every 16th partial of them
+// (coalesced rows, independent loads), then a pairwise tree over the 16 wave
+// sums in LDS.
+constexpr int kRedGroups = 16;
+__global__ void __launch_bounds__(64 * kRedGroups) k_mlp_reduce(const float *__restrict__ part, int nparts,
+                                                               float *__restrict__ grad, float *__restrict__ stat) {
+    __shared__ float sm[kRedGroups][64];
+    const int p = threadIdx.x & 63, gi = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + p;
+    float acc = 0.0f;
+    if (k < kNP + kStat)
+        for (int w = gi; w < nparts; w += kRedGroups) acc += part[(size_t)w * (kNP + kStat) + k];
+    sm[gi][p] = acc;
+    __syncthreads();
+    for (int h = kRedGroups / 2; h >= 1; h >>= 1) {
+        if (gi < h) sm[gi][p] += sm[gi + h][p];
+        __syncthreads();
+    }
+    if (gi == 0 && k < kNP + kStat) {
+        if (k < kNP) grad[k] = sm[0][p];
+        else stat[k - kNP] = sm[0][p];
     }
 }
 
@@ -508,8 +519,8 @@ static ro_status mlp_grad(ro_mlp *n, const uint16_t *x, const uint8_t *y, const 
     hipLaunchKernelGGL(k_mlp_grad, dim3(kTrainBlocks), dim3(64 * kWaves), 0, s, (const _Float16 *)x, y, mask, rows,
                        n->wh, n->p, n->part);
     RO_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((kNP + kStat + 255) / 256), dim3(256), 0, s, n->part, kPartials, n->g,
-                       n->stat);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kNP + kStat + 63) / 64), dim3(64 * kRedGroups), 0, s, n->part, kPartials,
+                       n->g, n->stat);
     RO_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_mlp_scale, dim3((kNP + 255) / 256), dim3(256), 0, s, n->g, n->stat);
     RO_HIP(hipGetLastError());

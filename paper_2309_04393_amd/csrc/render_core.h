@@ -4,6 +4,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace ro {
@@ -115,7 +117,7 @@ __device__ __forceinline__ void classify(float v, const ChanLds &ch, const float
     const float p = x * 255.0f;
     int e = (int)p;
     e = e > 255 ? 255 : e;
-    const int e1i = e < 255 ? e + 1 : 255;
+    const int e1i = e + (e < 255 ? 1 : 0);
     const float f = p - (float)e;
     const float4 ta = tf[e], tb = tf[e1i];
     al = ta.w + (tb.w - ta.w) * f;
@@ -335,17 +337,13 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     uint32_t cur_leaf = kInvalid;
     int cur_lod = -1, lod = 0;
     uint32_t emask = 0, missmask = 0;
-    // render-and-skip node (Alg. 1 renderAndSkipNode): samples k < hom_to lie
-    // in a node where every visible channel is empty or has one value; they
-    // composite the mix of those values (h_*), computed once per node
-    long long hom_to = 0;
-    float h_prod = 1.0f, h_sa = 0.0f, h_sr = 0.0f, h_sg = 0.0f, h_sb = 0.0f;
     uint64_t lvpack = 0;
     uint32_t nvisit = 0;
     int lc[3] = {-1, -1, -1};  // L0 origin of the last visited leaf (none yet)
     uint32_t last_key = kInvalid;  // (level, cell) of the last visit when uniform
     uint32_t have = 0;             // channels with a slot from the last visit
     uint32_t stamped = 0;          // with rates: channels whose current slot carries this frame's stamp
+    uint64_t rpk = 0;              // with rates: each channel's rate shift in the current visit (4 bits)
 
     // ray set-up in L0 voxel units, box interval, first sample index
     auto start = [&](int x, int y, bool valid) {
@@ -415,7 +413,6 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         rpace = 0;
         while (lod + 1 < L && (unsigned long long)k >= s_lv[lod + 1].K) ++lod;
         emask = missmask = 0;
-        hom_to = 0;
         lvpack = 0;
         nvisit = 0;
         lc[0] = lc[1] = lc[2] = -1;
@@ -531,13 +528,9 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 continue;
             }
         }
-        // inside a render-and-skip node: the node's constant mix stands for
-        // the sample (no descent, no lookup, no brick)
-        bool hs = HOMOG && k < hom_to;
-        uint32_t leaf = kInvalid;
-        if (!hs) leaf = node_at(leafl, iu[0] >> field(leafl.nsh, 0), iu[1] >> field(leafl.nsh, 1),
-                                iu[2] >> field(leafl.nsh, 2));
-        if (!hs && (leaf != cur_leaf || lod != cur_lod)) {
+        const uint32_t leaf = node_at(leafl, iu[0] >> field(leafl.nsh, 0), iu[1] >> field(leafl.nsh, 1),
+                                      iu[2] >> field(leafl.nsh, 2));
+        if (leaf != cur_leaf || lod != cur_lod) {
             flush();
             // with a traversal depth the decision node depends on the level too
             if (leaf != cur_leaf || (tdepth && lod != cur_lod)) {
@@ -550,8 +543,10 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 // every visible channel is empty or holds one value (and one
                 // holds a value) is rendered from those values and skipped
                 // (Alg. 1 renderAndSkipNode, Sec. 6.1: homogeneous for all
-                // channels); ancestors of a visited leaf are never such nodes
-                // either (metadata nest, so their descendants would be).
+                // channels): its samples are composited at once and the ray
+                // goes on past the node.  Ancestors of a visited leaf are never
+                // such nodes either (metadata nest, so their descendants would
+                // be).
                 int d0 = noskip ? dend : min(s0, dend);
                 if (lc[0] >= 0 && !noskip && !tdepth) {
                     while (d0 < D) {
@@ -563,6 +558,9 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     }
                 }
                 bool skipped = false;
+                long long rs_end = 0;   // render-and-skip: the node's exit sample,
+                uint32_t rs_node = 0;   // the node,
+                uint32_t rs_mask = 0;   // its homogeneous channels (none: no such node)
                 for (int dl = d0; dl <= dend; ++dl) {
                     const NodeLds nd = s_nd[dl];
                     const uint32_t node = node_at(nd, iu[0] >> field(nd.nsh, 0), iu[1] >> field(nd.nsh, 1),
@@ -630,46 +628,98 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                             skip_to = kn > k + 1 ? kn : k + 1;
                             ++k;
                             skipped = true;
-                        } else {
-                            // the samples up to the node's exit take the node's
-                            // values, mixed in visible-channel order as sampled
-                            // values are
-                            hom_to = kn > k + 1 ? kn : k + 1;
-                            h_prod = 1.0f;
-                            h_sa = h_sr = h_sg = h_sb = 0.0f;
-                            for (int j = 0; j < nvis; ++j) {
-                                if (!((hm >> j) & 1u)) continue;
-                                const ChanLds ch = s_ch[j];
-                                float al, r, gg, bb;
-                                classify((float)(nm[ch.c] & 0xFFFFu), ch, s_tf + j * 256, al, r, gg, bb);
-                                h_prod *= 1.0f - al;
-                                h_sa += al;
-                                h_sr += al * r;
-                                h_sg += al * gg;
-                                h_sb += al * bb;
-                            }
-                            hs = true;
+                        } else if constexpr (HOMOG) {
+                            // render-and-skip: composited after the descent
+                            rs_end = kn;
+                            rs_node = node;
+                            rs_mask = hm;
                         }
                         break;
+                    }
+                }
+                if constexpr (HOMOG) {
+                    if (rs_mask) {
+                        // The constant mix of the homogeneous channels (in
+                        // visible-channel order, as sampled values mix) for the
+                        // taken samples k, k + r, .. before the end of the span:
+                        // the node's exit, the volume's exit (the node may reach
+                        // beyond the volume, whose samples are void) and, with
+                        // the adaptive step, the next level threshold (r may
+                        // change there).  Composited one transparency factor at
+                        // a time, as sample by sample (early termination falls
+                        // on the same sample), with the colour summed in closed
+                        // form; then the ray goes on past the node.
+                        float hp = 1.0f, hsa = 0.0f, hsr = 0.0f, hsg = 0.0f, hsb = 0.0f;
+                        const uint32_t *rm = A.meta + (size_t)rs_node * m;
+                        for (int j = 0; j < nvis; ++j) {
+                            if (!((rs_mask >> j) & 1u)) continue;
+                            const ChanLds ch = s_ch[j];
+                            float al, r, gg, bb;
+                            classify((float)(rm[ch.c] & 0xFFFFu), ch, s_tf + j * 256, al, r, gg, bb);
+                            hp *= 1.0f - al;
+                            hsa += al;
+                            hsr += al * r;
+                            hsg += al * gg;
+                            hsb += al * bb;
+                        }
+                        double tb = INFINITY;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            if (d[a] == 0.0) continue;
+                            const double bound = d[a] > 0.0 ? (double)A.dims[a] : 0.0;
+                            tb = fmin(tb, (bound - o[a]) / d[a]);
+                        }
+                        long long end = (long long)floor(tb / A.step) - 1;
+                        end = rs_end < end ? rs_end : end;
+                        if (adaptive && lod + 1 < L && (long long)s_lv[lod + 1].K < end) end = s_lv[lod + 1].K;
+                        const long long rr = 1ll << rsh;
+                        long long n = (end - k + rr - 1) / rr;
+                        if (n < 1) n = 1;
+                        long long nt = n;
+                        if (hsa > 0.0f) {
+                            double tau = (double)hp;
+                            for (int q = 0; q < rsh; ++q) tau *= tau;
+                            const double t0 = Tr;
+                            for (long long i = 1; i <= n; ++i) {
+                                Tr *= tau;
+                                if (Tr <= one_minus_term) {
+                                    nt = i;
+                                    done = true;
+                                    break;
+                                }
+                            }
+                            const double sc = (t0 - Tr) / (double)hsa;
+                            Cr += sc * (double)hsr;
+                            Cg += sc * (double)hsg;
+                            Cb += sc * (double)hsb;
+                        }
+                        st_samples += (uint32_t)nt;
+                        st_hom += (uint32_t)nt;
+                        skip_to = k + n * rr;
+                        ++k;
+                        skipped = true;
                     }
                 }
                 if (skipped) {
                     cur_leaf = kInvalid;
                     continue;
                 }
-                if (hs) {
-                    cur_leaf = kInvalid;
-                } else {
-                    cur_leaf = leaf;
+                cur_leaf = leaf;
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) lc[a] = (iu[a] >> field(leafl.nsh, a)) << field(leafl.nsh, a);
-                }
+                for (int a = 0; a < 3; ++a) lc[a] = (iu[a] >> field(leafl.nsh, a)) << field(leafl.nsh, a);
             }
-            if (!hs) {
             cur_lod = lod;
             ++st_visits;
             missmask = 0;
             lvpack = 0;
+            if (rates) {
+                // the rate of each channel's clamped desired level (fixed within a visit)
+                rpk = 0;
+                for (int j = 0; j < nvis; ++j) {
+                    const ChanLds ch = s_ch[j];
+                    rpk |= (uint64_t)field(s_lv[min(max(lod, ch.lo), ch.hi)].raw, 0) << (4 * j);
+                }
+            }
             // Residency masks of the leaf give each channel the level it
             // samples (finest resident at or above the desired one).
             const uint16_t *lm = A.mask + (size_t)leaf * m;
@@ -794,25 +844,15 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
             }
             have = nhave;
             last_key = key;
-            }
         }
         ++st_samples;
         float prod = 1.0f, sa = 0.0f, sr = 0.0f, sg = 0.0f, sbl = 0.0f;
-        if (hs) {
-            ++st_hom;
-            prod = h_prod;
-            sa = h_sa;
-            sr = h_sr;
-            sg = h_sg;
-            sbl = h_sb;
-        } else {
         // channels taking part in this sample (all of them without rates)
         uint32_t part = vismask;
         if (rates) {
             part = 0;
             for (int j = 0; j < nvis; ++j) {
-                const ChanLds ch = s_ch[j];
-                const int rs = (int)field(s_lv[min(max(lod, ch.lo), ch.hi)].raw, 0);
+                const int rs = (int)((rpk >> (4 * j)) & 15u);
                 if (!(k & ((1ll << rs) - 1))) part |= 1u << j;
             }
             // misses and stamps per sample (a visit's samples differ in which
@@ -869,6 +909,33 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         float fr0 = 0.0f, fr1 = 0.0f, fr2 = 0.0f;
         const uint32_t E = EC ? (uint32_t)EC : (uint32_t)A.E;
         const size_t stride = EC ? slot_bytes(EC, BPV) : (size_t)A.slot_stride;
+        // in-brick voxel index and fractions of the sample at level lu
+        auto in_brick = [&](int lu) {
+            const LevLds lv = s_lv[lu];
+            uint32_t i0[3];
+            float fr[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int sft = (int)field(lv.raw, a);
+                const double ul = ldexp(u[a], -sft);
+                const int bo = (iu[a] >> field(lv.sh, a)) << A.Blog;
+                const double q = ul + 0.5 - (double)bo;
+                const int qi = (int)q;
+                i0[a] = (uint32_t)qi;
+                fr[a] = (float)(q - (double)qi);
+            }
+            idx = (i0[2] * E + i0[1]) * E + i0[0];
+            fr0 = fr[0];
+            fr1 = fr[1];
+            fr2 = fr[2];
+            lprev = lu;
+        };
+        // Gather, interpolate, classify and mix every channel with a slot.
+        // With UNI every such channel reads the visit's one level, whose
+        // coordinates are computed before the loop, so the FP64 position is
+        // not live across the channels.
+        auto sample_channels = [&](auto uni_c) {
+            constexpr bool UNI = decltype(uni_c)::value;
 #pragma unroll
         for (int g = 0; g < NV; g += kGroup) {
             if (g >= nvis) break;
@@ -878,27 +945,11 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
 #pragma unroll
             for (int jj = 0; jj < kGroup; ++jj) {
                 const int j = g + jj;
-                ok[jj] = j < nvis && slot[j] != kInvalid && ((part >> j) & 1u);
-                const int lu = (int)((lvpack >> (4 * j)) & 15u);
-                if (ok[jj] && lu != lprev) {
-                    const LevLds lv = s_lv[lu];
-                    uint32_t i0[3];
-                    float fr[3];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const int sft = (int)field(lv.raw, a);
-                        const double ul = ldexp(u[a], -sft);
-                        const int bo = (iu[a] >> field(lv.sh, a)) << A.Blog;
-                        const double q = ul + 0.5 - (double)bo;
-                        const int qi = (int)q;
-                        i0[a] = (uint32_t)qi;
-                        fr[a] = (float)(q - (double)qi);
-                    }
-                    idx = (i0[2] * E + i0[1]) * E + i0[0];
-                    fr0 = fr[0];
-                    fr1 = fr[1];
-                    fr2 = fr[2];
-                    lprev = lu;
+                ok[jj] = j < nvis && slot[j] != kInvalid;
+                if (rates) ok[jj] = ok[jj] && ((part >> j) & 1u);
+                if constexpr (!UNI) {
+                    const int lu = (int)((lvpack >> (4 * j)) & 15u);
+                    if (ok[jj] && lu != lprev) in_brick(lu);
                 }
                 fq[jj][0] = fr0;
                 fq[jj][1] = fr1;
@@ -934,8 +985,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 if (rates) {
                     // the channel stands for r_c base steps: transparency
                     // (1 - alpha)^r_c, colour weight r_c alpha
-                    const ChanLds ch = s_ch[j];
-                    const int rs = (int)field(s_lv[min(max(lod, ch.lo), ch.hi)].raw, 0);
+                    const int rs = (int)((rpk >> (4 * j)) & 15u);
                     float tr = 1.0f - al;
                     for (int q = 0; q < rs; ++q) tr *= tr;
                     const float w = (float)(1 << rs) * al;
@@ -957,6 +1007,13 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
             // bounds the registers held by loads in flight
             asm volatile("" ::: "memory");
         }
+        };
+        if (last_key != kInvalid) {
+            // one level for every channel with a slot (the visit's lookup key)
+            in_brick((int)(last_key >> 28));
+            sample_channels(std::true_type{});
+        } else {
+            sample_channels(std::false_type{});
         }
         if (sa > 0.0f) {
             if (rsh == 0 || rates) {

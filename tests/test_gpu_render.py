@@ -333,10 +333,11 @@ def plateau():
 
 def test_render_and_skip_full_residency(plateau):
     """Alg. 1 renderAndSkipNode with every brick resident and level 0
-    desired: images, requests and usage match the oracle, and the image is
-    bit-identical to the plain frame (the node's value goes through the same
-    table arithmetic as an interpolation of equal voxels) with fewer brick
-    reads and the same samples."""
+    desired: images, requests and usage match the oracle, and the image
+    equals the plain frame to rounding (the node's value goes through the
+    same table arithmetic as an interpolation of equal voxels; a node's
+    samples are composited at once, so the colour sums round differently)
+    with fewer brick reads and the same samples."""
     p = Pair(plateau, 16, (4, 4, 4), 4, n_slots=146)
     assert (p.upload(0, p.gpu.all_ids()) == 1).all()
     p.check_masks()
@@ -348,7 +349,7 @@ def test_render_and_skip_full_residency(plateau):
         p.check_frame(res, f"rskip-full-{flags}")
         stats.append(st.cpu().numpy())
         imgs.append(res["gpu"])
-    assert np.array_equal(imgs[0], imgs[1])
+    assert np.abs(imgs[0] - imgs[1]).max() < 1e-6
     assert stats[1][1] < 0.7 * stats[0][1]  # brick reads
     assert stats[1][0] == stats[0][0] and stats[1][6] > 0 and stats[0][6] == 0
 
