@@ -827,6 +827,9 @@ def prefetch_bench(train_seeds=tuple(range(1000, 1010)), eval_seeds=tuple(range(
            "eval_paths": list(eval_seeds), "train_s": t_train,
            "summary": {pol: {k: agg(k, pol) for k in ("frames_to_converge", "first_below_1pct", "mean_missing",
                                                        "bytes_streamed")} for pol in ("plain", "learned")},
+           "per_path": [{"seed": e["seed"], **{pol: {k: e[pol][k] for k in
+                         ("frames_to_converge", "first_below_1pct", "mean_missing", "bytes_streamed", "extra",
+                          "precision")} for pol in ("plain", "learned")}} for e in ev],
            "paths": ev}
     del store, scene
     torch.cuda.empty_cache()
