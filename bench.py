@@ -97,8 +97,11 @@ def profile_summary(trace_dir, fetch_dir, write_dir, last, workload, kernel="k_r
         rows = _csv_rows(d, "counter_collection.csv")
         k = sorted((r for r in rows if kernel in r["Kernel_Name"] and r["Counter_Name"].startswith(name)),
                    key=lambda r: int(r["Dispatch_Id"]))
+        # the calibration copies are the largest copies after the last frame
+        # (earlier copies are set-up and uploads of other sizes)
+        end = int(k[-1]["Dispatch_Id"]) if k else -1
         cp = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
-              and r["Counter_Name"].startswith(name)]
+              and r["Counter_Name"].startswith(name) and int(r["Dispatch_Id"]) > end]
         return [float(r["Counter_Value"]) for r in k][-last:], (max(cp) if cp else None)
 
     fetch, fcopy = counter(fetch_dir, "FETCH_SIZE")
