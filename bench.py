@@ -615,7 +615,9 @@ def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True, max_batch=64):
     one request at a time through the frame kernel, then p50/p99 latency over
     `seconds` of arrivals at `rate` and at 70% of the batched capacity (a
     request still unfinished 5 s after the arrivals stop counts as
-    infinitely late)."""
+    infinitely late).  The same measurements with continuous admission
+    (requests admitted one at a time while others render) go under
+    "continuous", with the 70%-load trace shared with the batched loop."""
     import torch
 
     import synth
@@ -673,11 +675,13 @@ def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True, max_batch=64):
     shed_loop.run(sub[:4])  # graph capture
     reset_trace(sub)
 
-    def at_rate(lam, seed, max_wait=None):
-        lp = loop if max_wait is None else shed_loop
+    def at_rate(lam, seed, max_wait=None, lp=None):
+        if lp is None:
+            lp = loop if max_wait is None else shed_loop
         trace = make_trace(scene, lam, seconds, arrival_seed=seed)
         lp.stats.zero_()
         nb0 = lp.n_batches
+        na0 = len(lp.in_flight_at_admission)
         wall = lp.run(trace, deadline=seconds + 5.0, max_wait=max_wait)
         st = lp.stats.cpu().numpy()
         lat = latency_summary(trace)
@@ -686,13 +690,19 @@ def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True, max_batch=64):
         shed = sum(1 for r in trace if r.shed)
         res = {"rate_req_per_s": lam, "seconds": seconds, "requests": len(trace), "completed": done,
                "latency_ms": {k: v for k, v in lat.items() if k not in ("n", "completed")},
-               "wall_s": wall, "served_req_per_s": done / wall, "samples_per_s": float(st[0]) / wall,
-               "batches": len(sizes), "mean_batch": float(np.mean(sizes)) if sizes else 0.0}
+               "wall_s": wall, "served_req_per_s": done / wall, "samples_per_s": float(st[0]) / wall}
+        if lp.continuous:
+            fl = lp.in_flight_at_admission[na0:]
+            res["mean_unfinished_at_admission"] = float(np.mean(fl)) if fl else 0.0
+        else:
+            res["batches"] = len(sizes)
+            res["mean_batch"] = float(np.mean(sizes)) if sizes else 0.0
         if max_wait is not None:
             res["max_queue_wait_s"] = max_wait
-            res["max_batch_work_items"] = lp.max_tiles
+            res["max_work_items_in_flight" if lp.continuous else "max_batch_work_items"] = lp.max_tiles
             res["shed"] = shed
-        log(f"serving at {lam:.1f} requests/s (max wait {max_wait}): {done} of {len(trace)} done, {shed} shed")
+        log(f"serving at {lam:.1f} requests/s (max wait {max_wait}, continuous {lp.continuous}): "
+            f"{done} of {len(trace)} done, {shed} shed")
         return res
 
     out["stated_load"] = at_rate(rate, 3000)
@@ -700,8 +710,23 @@ def serve_bench(rate=400.0, seconds=10.0, n_sat=160, graph=True, max_batch=64):
     # bounded latency
     out["stated_load_shedding"] = at_rate(rate, 3000, max_wait=0.1)
     out["load_70pct_capacity"] = at_rate(0.7 * cap, 3002)
+
+    # continuous admission: the saturated throughput, then the same traces
+    cloop = ServingLoop(scene, out_budget=4 << 30, max_requests=max_batch, max_tiles=1 << 17, continuous=True)
+    cloop.run(sub[:8])  # first-touch
+    reset_trace(sub)
+    cloop.stats.zero_()
+    wc = cloop.run(sub)
+    sc = float(cloop.stats.cpu().numpy()[0])
+    reset_trace(sub)
+    cshed = ServingLoop(scene, out_budget=4 << 30, max_requests=max_batch, max_tiles=1024, continuous=True)
+    out["continuous"] = {
+        "saturated": {"requests": len(sub), "samples_per_s": sc / wc, "req_per_s": len(sub) / wc,
+                      "vs_batched": (sc / wc) / (sb / wb), "same_samples": sc == sb},
+        "stated_load_shedding": at_rate(rate, 3000, max_wait=0.1, lp=cshed),
+        "load_70pct_capacity": at_rate(0.7 * cap, 3002, lp=cloop)}
     log(f"serving: {json.dumps(out)}")
-    del loop, shed_loop, scene
+    del loop, shed_loop, cloop, cshed, scene
     torch.cuda.empty_cache()
     return out
 

@@ -562,6 +562,38 @@ ro_status ro_serve_wait(ro_server *s, uint64_t ticket);
 ro_status ro_serve_launch(ro_server *s, uint32_t n, const ro_frame_desc *fds, float *const *rgba_dev,
                           uint64_t *ticket);
 
+/* Continuous admission (an addition to the paper's method, next to the
+ * batches above): requests are admitted one at a time, whenever the caller
+ * likes, also while others render.  The server appends the request's work
+ * items to a ring of max_tiles (rounded up to a power of two) entries in
+ * mapped pinned host memory and publishes them; the workgroups of every
+ * running serving kernel take the next published item as they free up, and
+ * each call also launches a kernel (the 16-channel instance, at most one
+ * workgroup per compute unit, alternating between two non-blocking streams
+ * of default priority) for the compute units that have emptied.  A kernel's
+ * workgroups leave as soon as no published item is left: no kernel ever
+ * waits for the host.  The same per-ray code as ro_render runs, so the image
+ * is the same as the frame kernel's.  Up to max_requests requests are
+ * unfinished at once (one descriptor slot each).
+ *
+ * ro_serve_enqueue: fd as for ro_serve_prepare (no diagnostic outputs, no
+ * homogeneous nodes, rates or traversal depths), rgba_dev the [H][W][4]
+ * float output (256-byte aligned).  RO_E_CAPACITY, with nothing admitted,
+ * when every slot holds an unfinished request or the ring has no room for
+ * the request's items (retry after completions).  *ticket names the request
+ * for ro_serve_done.  The caller keeps the output and the transfer-function
+ * tables alive until the request has finished.  Batches and continuous
+ * admission may be mixed (their queues are separate); the same rules on
+ * streaming and residency updates apply (no changes while requests are
+ * unfinished).  Tickets are 32-bit serials from 1 on (a server admits fewer
+ * than 2^32 requests). */
+ro_status ro_serve_enqueue(ro_server *s, const ro_frame_desc *fd, float *rgba_dev, uint64_t *ticket);
+/* *done = 1 once the request's last work item is written (the kernel posts
+ * it to mapped host memory), else 0.  RO_E_ARG for a ticket never issued. */
+ro_status ro_serve_done(ro_server *s, uint64_t ticket, int32_t *done);
+/* Waits until every admitted request has finished and its kernels ended. */
+ro_status ro_serve_drain(ro_server *s);
+
 /* Thread-local message of the last failing call ("" if none). */
 const char *ro_last_error(void);
 

@@ -92,7 +92,7 @@ struct QueueLaunch {
 
 template <int NV, int BPV, bool AOV, int EC, bool HOMOG = false>
 static hipError_t launch_one(const RenderArgs &A, const QueueLaunch &Q, hipStream_t s) {
-    const size_t lds = render_lds_bytes(NV);
+    const size_t lds = render_lds_bytes(NV, HOMOG);
     hipError_t e = hipFuncSetAttribute((const void *)k_render<NV, BPV, AOV, EC, HOMOG>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -171,10 +171,19 @@ constexpr int kRenderLanes = RO_LANES;
 // Serving work items: up to kSegBlocks 8 x 8-pixel blocks of one request.
 constexpr uint32_t kSegBlocks = 96;
 
+// A lane's span of a node that is homogeneous for every visible channel:
+// the transparency of one taken sample, the transparency when the span
+// began, and the constant mix's summed opacity and opacity-weighted colour.
+struct HomLane {
+    double tau, t0;
+    float hsa, hsr, hsg, hsb;
+};
+
 // Dynamic LDS of a workgroup: NV transfer-function tables, then one slot
-// word per lane and visible channel.
-__host__ __device__ constexpr size_t render_lds_bytes(int nv) {
-    return (size_t)nv * 256 * 16 + (size_t)nv * kRenderLanes * 4;
+// word per lane and visible channel, then (kernels with render-and-skip)
+// one HomLane per lane.
+__host__ __device__ constexpr size_t render_lds_bytes(int nv, bool homog = false) {
+    return (size_t)nv * 256 * 16 + (size_t)nv * kRenderLanes * 4 + (homog ? kRenderLanes * sizeof(HomLane) : 0);
 }
 
 // Slot of each visible channel for a lane's current visit, kept in LDS (one
@@ -344,6 +353,11 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     uint32_t have = 0;             // channels with a slot from the last visit
     uint32_t stamped = 0;          // with rates: channels whose current slot carries this frame's stamp
     uint64_t rpk = 0;              // with rates: each channel's rate shift in the current visit (4 bits)
+    // render-and-skip: the lane composites a homogeneous span, one taken
+    // sample per wave iteration, until skip_to (its state in LDS)
+    bool hom_on = false;
+    HomLane *hl = nullptr;
+    if constexpr (HOMOG) hl = (HomLane *)((uint32_t *)(s_tf + 256 * NV) + NV * kRenderLanes) + threadIdx.x;
 
     // ray set-up in L0 voxel units, box interval, first sample index
     auto start = [&](int x, int y, bool valid) {
@@ -419,6 +433,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         last_key = kInvalid;
         have = 0;
         stamped = 0;
+        hom_on = false;
 #pragma unroll
         for (int j = 0; j < NV; ++j) slot[j] = kInvalid;
     };
@@ -477,7 +492,9 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         }
         const bool active = has && !done && k <= kend;
         const long long gap = skip_to - k;
-        uint32_t need = !active ? 0xFFFFFFFFu : (gap > 0 ? (gap < 0x7FFFFFFFll ? (uint32_t)gap : 0x7FFFFFFFu) : 0u);
+        // (a lane compositing a homogeneous span takes every iteration)
+        uint32_t need = !active ? 0xFFFFFFFFu
+                                : (gap > 0 && !hom_on ? (gap < 0x7FFFFFFFll ? (uint32_t)gap : 0x7FFFFFFFu) : 0u);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) need = min(need, (uint32_t)__shfl_xor((int)need, o, 64));
         if (need == 0xFFFFFFFFu) {
@@ -492,6 +509,27 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         }
         ++st_iters;  // a stepping iteration of the wave (lane busy or idle)
         if (!active) continue;
+        if constexpr (HOMOG) {
+            if (hom_on) {
+                // the next taken sample of the span: one transparency factor,
+                // as sample by sample (early termination falls on the same
+                // sample); the colour is summed in closed form at the end
+                Tr *= hl->tau;
+                ++st_samples;
+                ++st_hom;
+                const bool term = Tr <= one_minus_term;
+                k += ADAPT ? (1ll << rpace) : 1;
+                if (term || k >= skip_to) {
+                    const double sc = (hl->t0 - Tr) / (double)hl->hsa;
+                    Cr += sc * (double)hl->hsr;
+                    Cg += sc * (double)hl->hsg;
+                    Cb += sc * (double)hl->hsb;
+                    hom_on = false;
+                    done = term;
+                }
+                continue;
+            }
+        }
         if (k < skip_to) {
             // a skipping lane keeps the pace of the sampling lanes (one base
             // step, or the band's distance with the adaptive step) so the
@@ -641,14 +679,13 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     if (rs_mask) {
                         // The constant mix of the homogeneous channels (in
                         // visible-channel order, as sampled values mix) for the
-                        // taken samples k, k + r, .. before the end of the span:
-                        // the node's exit, the volume's exit (the node may reach
+                        // taken samples k, k + r, .. of the span: up to the
+                        // node's exit, the volume's exit (the node may reach
                         // beyond the volume, whose samples are void) and, with
                         // the adaptive step, the next level threshold (r may
-                        // change there).  Composited one transparency factor at
-                        // a time, as sample by sample (early termination falls
-                        // on the same sample), with the colour summed in closed
-                        // form; then the ray goes on past the node.
+                        // change there).  The lane composites them one per
+                        // wave iteration from here on, without gathers, then
+                        // goes on past the node.
                         float hp = 1.0f, hsa = 0.0f, hsr = 0.0f, hsg = 0.0f, hsb = 0.0f;
                         const uint32_t *rm = A.meta + (size_t)rs_node * m;
                         for (int j = 0; j < nvis; ++j) {
@@ -669,34 +706,32 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                             const double bound = d[a] > 0.0 ? (double)A.dims[a] : 0.0;
                             tb = fmin(tb, (bound - o[a]) / d[a]);
                         }
-                        long long end = (long long)floor(tb / A.step) - 1;
-                        end = rs_end < end ? rs_end : end;
+                        // rs_end and the box's last sample lie a whole step
+                        // inside their boxes, so they are taken too; samples
+                        // from the next level threshold on are not
+                        long long end = (long long)floor(tb / A.step);
+                        end = rs_end + 1 < end ? rs_end + 1 : end;
                         if (adaptive && lod + 1 < L && (long long)s_lv[lod + 1].K < end) end = s_lv[lod + 1].K;
                         const long long rr = 1ll << rsh;
                         long long n = (end - k + rr - 1) / rr;
                         if (n < 1) n = 1;
-                        long long nt = n;
+                        skip_to = k + n * rr;
                         if (hsa > 0.0f) {
                             double tau = (double)hp;
                             for (int q = 0; q < rsh; ++q) tau *= tau;
-                            const double t0 = Tr;
-                            for (long long i = 1; i <= n; ++i) {
-                                Tr *= tau;
-                                if (Tr <= one_minus_term) {
-                                    nt = i;
-                                    done = true;
-                                    break;
-                                }
-                            }
-                            const double sc = (t0 - Tr) / (double)hsa;
-                            Cr += sc * (double)hsr;
-                            Cg += sc * (double)hsg;
-                            Cb += sc * (double)hsb;
+                            hl->tau = tau;
+                            hl->t0 = Tr;
+                            hl->hsa = hsa;
+                            hl->hsr = hsr;
+                            hl->hsg = hsg;
+                            hl->hsb = hsb;
+                            hom_on = true;
+                        } else {
+                            // nothing to composite: the span is skipped
+                            st_samples += (uint32_t)n;
+                            st_hom += (uint32_t)n;
+                            ++k;
                         }
-                        st_samples += (uint32_t)nt;
-                        st_hom += (uint32_t)nt;
-                        skip_to = k + n * rr;
-                        ++k;
                         skipped = true;
                     }
                 }

@@ -548,6 +548,10 @@ _sig("ro_serve_poll", c_i32, [c_vp, c_u64, _P(c_i32)])
 _sig("ro_serve_wait", c_i32, [c_vp, c_u64])
 _sig("ro_serve_work_items", c_i32, [c_i32, c_i32, _P(c_u32)])
 _sig("ro_serve_request_done", c_i32, [c_vp, c_u64, c_u32, _P(c_i32)])
+_sig("ro_serve_enqueue", c_i32, [c_vp, c_vp, c_vp, _P(c_u64)])
+_sig("ro_serve_done", c_i32, [c_vp, c_u64, _P(c_i32)])
+_sig("ro_serve_drain", c_i32, [c_vp])
+E_CAPACITY = -2
 
 
 def serve_work_items(W: int, H: int) -> int:
@@ -609,3 +613,22 @@ class Server:
         d = c_i32()
         _check(_lib.ro_serve_request_done(self.h, ticket, r, ctypes.byref(d)), "ro_serve_request_done")
         return bool(d.value)
+
+    def enqueue(self, fd, out):
+        """Continuous admission of one request; its ticket, or None when
+        every request slot is busy or the ring is full (nothing admitted)."""
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= 4 * fd.width * fd.height
+        t = c_u64()
+        code = _lib.ro_serve_enqueue(self.h, ctypes.byref(fd), _dev_ptr(out), ctypes.byref(t))
+        if code == E_CAPACITY:
+            return None
+        _check(code, "ro_serve_enqueue")
+        return int(t.value)
+
+    def done(self, ticket: int) -> bool:
+        d = c_i32()
+        _check(_lib.ro_serve_done(self.h, ticket, ctypes.byref(d)), "ro_serve_done")
+        return bool(d.value)
+
+    def drain(self):
+        _check(_lib.ro_serve_drain(self.h), "ro_serve_drain")

@@ -11,6 +11,13 @@ renders and the tail of one overlaps the head of the next on the device.
 With graph submission each half's device work (descriptor copy, queue reset,
 persistent kernel) is a captured graph replayed with new contents.
 
+With continuous admission (continuous=True) there are no batches: each
+queued request is admitted on its own as soon as a request slot, room in
+the server's work-item ring and output memory are free, also while others
+render; the workgroups of the running serving kernels take its work items
+as they free up (and the launch made for it fills emptied compute units),
+so a request arriving mid-batch does not wait for a batch to retire.
+
 Latency of a request = its completion on the device (the kernel posts each
 request's completion to mapped host memory when its last pixels are
 written; the loop polls) - its arrival.  Within a batch the smallest
@@ -88,6 +95,7 @@ class Request:
     done: float = math.nan
     shed: bool = False
     mem: tuple = None
+    ticket: int = 0
     fd: object = field(default=None, repr=False)
 
     @property
@@ -108,15 +116,19 @@ class Batch:
 
 class ServingLoop:
     def __init__(self, scene, out_budget: int = 2 << 30, max_requests: int = 64, max_tiles: int = 1 << 16,
-                 step: float = 0.5, graph: bool = True, lod_bias: float = 1.0, term_alpha: float = 0.99):
+                 step: float = 0.5, graph: bool = True, lod_bias: float = 1.0, term_alpha: float = 0.99,
+                 continuous: bool = False):
         self.s = scene
         self.server = resoct.Server(scene.tree, max_requests, max_tiles)
         self.arena = Arena(out_budget)
         self.max_requests, self.max_tiles = max_requests, max_tiles
         self.step, self.graph, self.lod_bias, self.term_alpha = step, graph, lod_bias, term_alpha
+        self.continuous = continuous
+        self.ring_items = 1 << max(0, (max_tiles - 1).bit_length())  # the server's ring (a power of two)
         self.stats = torch.zeros(8, dtype=torch.int64, device="cuda")
         self.n_batches = 0
         self.batch_sizes = []
+        self.in_flight_at_admission = []  # continuous: requests unfinished when each one was admitted
 
     def frame_desc(self, r: Request, out: torch.Tensor):
         return resoct.frame_desc(r.frame, r.cam, r.W, r.H, self.step, r.chans, r.tf, self.s.vol.n_levels,
@@ -163,6 +175,8 @@ class ServingLoop:
         queued request that has waited longer is shed (r.shed = True, never
         rendered): load shedding keeps the latency of the served requests
         bounded when arrivals exceed the capacity."""
+        if self.continuous:
+            return self._run_continuous(trace, on_done, idle_sleep, deadline, max_wait)
         # the server's streams do not wait for work queued on torch's streams
         torch.cuda.synchronize()
         clock = time.perf_counter
@@ -212,6 +226,68 @@ class ServingLoop:
             if not progressed:
                 if inflight or i < n:
                     time.sleep(idle_sleep)
+        return clock() - t0
+
+
+    def _run_continuous(self, trace, on_done, idle_sleep, deadline, max_wait):
+        torch.cuda.synchronize()
+        clock = time.perf_counter
+        t0 = clock()
+        i, n = 0, len(trace)
+        queue, inflight = [], []
+        while i < n or queue or inflight:
+            now = clock() - t0
+            if deadline is not None and now >= deadline:
+                i = n
+                queue = []
+                if not inflight:
+                    break
+            progressed = False
+            while i < n and trace[i].arrival <= now:
+                queue.append(trace[i])
+                i += 1
+                progressed = True
+            for r in list(inflight):
+                if self.server.done(r.ticket):
+                    r.done = clock() - t0
+                    if on_done is not None:
+                        on_done(r, self.arena.view(r.mem[0], 4 * r.W * r.H))
+                    self.arena.free(*r.mem)
+                    r.mem = None
+                    inflight.remove(r)
+                    progressed = True
+            if max_wait is not None and queue and now - queue[0].arrival > max_wait:
+                keep = []
+                for r in queue:
+                    if now - r.arrival > max_wait:
+                        r.shed = True
+                    else:
+                        keep.append(r)
+                queue[:] = keep
+                progressed = True
+            # admit in arrival order while a slot, ring room and output memory are free
+            while queue:
+                r = queue[0]
+                if r.tiles > self.ring_items or r.image_bytes > self.arena.size:
+                    raise ValueError(f"request {r.rid} ({r.W}x{r.H}) can never be admitted")
+                mem = self.arena.alloc(r.image_bytes)
+                if mem is None:
+                    break
+                out = self.arena.view(mem[0], 4 * r.W * r.H)
+                fd = self.frame_desc(r, out)
+                t = self.server.enqueue(fd, out)
+                if t is None:
+                    self.arena.free(*mem)
+                    break
+                queue.pop(0)
+                r.mem, r.admitted, r.ticket = mem, now, t
+                self.in_flight_at_admission.append(len(inflight))
+                inflight.append(r)
+                progressed = True
+            if not progressed:
+                if inflight or i < n:
+                    time.sleep(idle_sleep)
+        self.server.drain()
         return clock() - t0
 
 
@@ -304,3 +380,4 @@ def reset_trace(trace):
         r.shed = False
         r.mem = None
         r.fd = None
+        r.ticket = 0

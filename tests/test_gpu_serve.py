@@ -267,3 +267,100 @@ def test_load_shedding_bounds_queue_wait(scene):
     lat = latency_summary(trace)
     assert lat["n"] == len(served) and np.isfinite(lat["p99_ms"])
     _report("serve-shedding", requests=len(trace), served=len(served), shed=len(shed), **lat)
+
+
+def _wait_done(srv, tickets, limit_s=60.0):
+    import time
+    t0 = time.perf_counter()
+    while not all(srv.done(t) for t in tickets):
+        assert time.perf_counter() - t0 < limit_s, "continuous requests did not finish"
+        time.sleep(1e-4)
+
+
+def test_continuous_admission_equals_frame_kernel(scene):
+    """Requests admitted one at a time into a small ring (4 slots, 32 work
+    items, so admissions wait for completions and the ring wraps), some
+    while others render, a large one among them: every image and every
+    request's sample statistics equal the frame kernel's."""
+    import time
+    reqs = []
+    for i in range(5):
+        reqs += _requests(scene.src, 40 + i, n=6)
+    big = _requests(scene.src, 44, n=1)[0]
+    big.update(W=400, H=300, cam=dict(big["cam"], tx=big["cam"]["ty"] * 400 / 300))
+    reqs.insert(2, big)
+    rig = Rig(scene, reqs)
+    ref, st_ref = rig.frame_kernel()
+    srv = resoct.Server(scene.tree, max_requests=4, max_tiles=32)
+    items = sum(resoct.serve_work_items(r["W"], r["H"]) for r in reqs)
+    assert items > 2 * 32 and resoct.serve_work_items(400, 300) <= 32
+    rig.stats.zero_()
+    outs = [rig.out(k) for k in range(len(reqs))]
+    torch.cuda.synchronize()
+    tickets, waits = [], 0
+    t0 = time.perf_counter()
+    for k in range(len(reqs)):
+        while True:
+            t = srv.enqueue(rig.fd(k), outs[k])
+            if t is not None:
+                break
+            waits += 1  # every slot busy or the ring full: wait for completions
+            assert time.perf_counter() - t0 < 60.0, "admission never succeeded"
+            time.sleep(1e-4)
+        tickets.append(t)
+    _wait_done(srv, tickets)
+    srv.drain()
+    assert tickets == list(range(tickets[0], tickets[0] + len(reqs)))
+    st = rig.stats.cpu().numpy()
+    exact = sum(_same(rig.image(k, outs[k]), ref[k], f"cont-{k}") for k in range(len(reqs)))
+    assert np.array_equal(st[:, :5], st_ref[:, :5]), "per-request sample statistics differ"
+    with pytest.raises(resoct.ResoctError):
+        srv.done(tickets[-1] + 1)
+    _report("serve-continuous", requests=len(reqs), work_items=items, admission_waits=waits,
+            bit_exact=f"{exact}/{len(reqs)}")
+
+
+def test_continuous_mixed_with_batches(scene):
+    """Batches and continuous admission on one server, interleaved: both
+    queues' images equal the frame kernel's."""
+    rig = Rig(scene, _requests(scene.src, 50, n=6))
+    ref, _ = rig.frame_kernel()
+    srv = resoct.Server(scene.tree, max_requests=8, max_tiles=256)
+    outs = [rig.out(k) for k in range(6)]
+    torch.cuda.synchronize()
+    tc = [srv.enqueue(rig.fd(k, stats=False), outs[k]) for k in (0, 1)]
+    tb = srv.launch([rig.fd(k, stats=False) for k in (2, 3)], [outs[2], outs[3]])
+    tc += [srv.enqueue(rig.fd(k, stats=False), outs[k]) for k in (4, 5)]
+    assert None not in tc
+    _wait_done(srv, tc)
+    srv.wait(tb)
+    srv.drain()
+    exact = sum(_same(rig.image(k, outs[k]), ref[k], f"mixed-{k}") for k in range(6))
+    _report("serve-continuous-mixed", requests=6, bit_exact=f"{exact}/6")
+
+
+def test_serving_loop_continuous(scene):
+    """The real-time loop with continuous admission under a small output
+    budget: every request completes, the budget holds, requests are admitted
+    while others are unfinished, and every image equals the frame kernel's."""
+    trace = make_trace(scene, rate=300.0, duration=0.25, n_clients=8, arrival_seed=3004)
+    assert len(trace) > 20
+    budget = 3 * 16 * 1920 * 1080
+    loop = ServingLoop(scene, out_budget=budget, max_requests=8, max_tiles=1 << 14, continuous=True)
+    got = {}
+    loop.run(trace, on_done=lambda r, img: got.__setitem__(r.rid, img.cpu().numpy().copy()))
+    assert len(got) == len(trace)
+    assert loop.arena.used == 0 and loop.arena.peak <= loop.arena.size
+    assert max(loop.in_flight_at_admission) >= 1, "no request was admitted while another was unfinished"
+    lat = latency_summary(trace)
+    assert lat["n"] == len(trace) and np.isfinite(lat["p99_ms"])
+    out = torch.empty(4 * 1920 * 1080, dtype=torch.float32, device="cuda")
+    n_exact = 0
+    for r in trace:
+        fd = resoct.frame_desc(r.frame, r.cam, r.W, r.H, 0.5, r.chans, r.tf, scene.vol.n_levels)
+        scene.tree.render(fd, out)
+        ref = gpu_rgba(out, r.H, r.W)
+        img = got[r.rid][: r.H * r.W * 4].reshape(r.H, r.W, 4).astype(np.float64)
+        n_exact += _same(img, ref, f"cloop-{r.rid}")
+    _report("serve-loop-continuous", requests=len(trace), mean_in_flight=np.mean(loop.in_flight_at_admission),
+            bit_exact=f"{n_exact}/{len(trace)}", peak_mb=loop.arena.peak / 2**20, **lat)
