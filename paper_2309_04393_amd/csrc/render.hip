@@ -24,9 +24,10 @@ namespace ro {
 
 // Workgroups of kRenderLanes lanes (768: 3 waves per SIMD, up to 168 VGPRs),
 // one per CU: one copy of the frame's LDS tables plus the per-lane slot
-// words.  The 16-channel instantiations for 32^3 bricks keep 12 bytes per
-// lane in scratch (the others none).  1024 lanes (4 waves per SIMD, 128
-// VGPRs) spill more and measured 1-10 % slower, 512 lanes 35 % slower.
+// words.  The 16-channel instantiations keep 8 to 40 bytes per lane in
+// scratch (12 for 32^3 bricks without the options), some 8-channel ones 8
+// to 12, the others none.  1024 lanes (4 waves per SIMD, 128 VGPRs) spill
+// more and measured 1-10 % slower, 512 lanes 35 % slower.
 
 // Lanes refill only when the whole wave is idle: a wave then takes a whole
 // new 8 x 8 block and its rays start together.  Refilling single lanes as

@@ -348,7 +348,8 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     uint32_t emask = 0, missmask = 0;
     uint64_t lvpack = 0;
     uint32_t nvisit = 0;
-    int lc[3] = {-1, -1, -1};  // L0 origin of the last visited leaf (none yet)
+    int lc[3] = {-1, -1, -1};  // L0 origin of the last visited leaf or skipped node (none yet)
+    int lcd = 0;                // its depth: the nodes above it are known not to be skipped
     uint32_t last_key = kInvalid;  // (level, cell) of the last visit when uniform
     uint32_t have = 0;             // channels with a slot from the last visit
     uint32_t stamped = 0;          // with rates: channels whose current slot carries this frame's stamp
@@ -430,6 +431,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         lvpack = 0;
         nvisit = 0;
         lc[0] = lc[1] = lc[2] = -1;
+        lcd = 0;
         last_key = kInvalid;
         have = 0;
         stamped = 0;
@@ -492,9 +494,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         }
         const bool active = has && !done && k <= kend;
         const long long gap = skip_to - k;
-        // (a lane compositing a homogeneous span takes every iteration)
-        uint32_t need = !active ? 0xFFFFFFFFu
-                                : (gap > 0 && !hom_on ? (gap < 0x7FFFFFFFll ? (uint32_t)gap : 0x7FFFFFFFu) : 0u);
+        uint32_t need = !active ? 0xFFFFFFFFu : (gap > 0 ? (gap < 0x7FFFFFFFll ? (uint32_t)gap : 0x7FFFFFFFu) : 0u);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) need = min(need, (uint32_t)__shfl_xor((int)need, o, 64));
         if (need == 0xFFFFFFFFu) {
@@ -504,6 +504,36 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
             continue;
         }
         if (need > 0) {
+            // every active lane is in an empty node or a homogeneous span:
+            // the wave jumps; a lane in a span composites the span's samples
+            // it passes, one transparency factor each (a few instructions
+            // per sample, all lanes at once)
+            if constexpr (HOMOG) {
+                if (active && hom_on) {
+                    const long long rr = ADAPT ? (1ll << rpace) : 1;
+                    const long long m = ((long long)need + rr - 1) / rr;
+                    const double tau = hl->tau;
+                    bool term = false;
+                    long long i = 0;
+                    while (i < m && !term) {
+                        Tr *= tau;
+                        ++i;
+                        term = Tr <= one_minus_term;
+                    }
+                    st_samples += (uint32_t)i;
+                    st_hom += (uint32_t)i;
+                    k += i * rr;
+                    if (term || k >= skip_to) {
+                        const double sc = (hl->t0 - Tr) / (double)hl->hsa;
+                        Cr += sc * (double)hl->hsr;
+                        Cg += sc * (double)hl->hsg;
+                        Cb += sc * (double)hl->hsb;
+                        hom_on = false;
+                        done = term;
+                    }
+                    continue;
+                }
+            }
             k += need;
             continue;
         }
@@ -581,13 +611,15 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 // every visible channel is empty or holds one value (and one
                 // holds a value) is rendered from those values and skipped
                 // (Alg. 1 renderAndSkipNode, Sec. 6.1: homogeneous for all
-                // channels): its samples are composited at once and the ray
-                // goes on past the node.  Ancestors of a visited leaf are never
-                // such nodes either (metadata nest, so their descendants would
-                // be).
+                // channels): its samples are composited and the ray goes on
+                // past the node.  Ancestors of a visited leaf are never such
+                // nodes either (metadata nest, so their descendants would be),
+                // and the ancestors of a skipped node were tested and found
+                // not to be skipped: the shared levels above the last visited
+                // leaf or skipped node are not tested again.
                 int d0 = noskip ? dend : min(s0, dend);
                 if (lc[0] >= 0 && !noskip && !tdepth) {
-                    while (d0 < D) {
+                    while (d0 < lcd) {
                         const uint32_t sh = s_nd[d0].nsh;
                         if (((iu[0] ^ lc[0]) >> field(sh, 0)) | ((iu[1] ^ lc[1]) >> field(sh, 1)) |
                             ((iu[2] ^ lc[2]) >> field(sh, 2)))
@@ -596,7 +628,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     }
                 }
                 bool skipped = false;
-                long long rs_end = 0;   // render-and-skip: the node's exit sample,
+                long long rs_end = 0;   // render-and-skip: the first sample past the node or the volume,
                 uint32_t rs_node = 0;   // the node,
                 uint32_t rs_mask = 0;   // its homogeneous channels (none: no such node)
                 for (int dl = d0; dl <= dend; ++dl) {
@@ -652,6 +684,9 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     // (without skipping, empty nodes are stepped through;
                     // render-and-skip changes the image, so it stays on)
                     if ((all_empty && !noskip) || rskip) {
+                        // exit of the node (and, for render-and-skip, of the
+                        // volume: a node may reach past it, and void samples
+                        // are not composited)
                         double te = INFINITY;
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
@@ -660,15 +695,33 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                             const double lo_a = (double)((iu[a] >> sh) << sh);
                             const double bound = d[a] > 0.0 ? lo_a + (double)(1 << sh) : lo_a;
                             te = fmin(te, (bound - o[a]) / d[a]);
+                            if (!all_empty) te = fmin(te, ((d[a] > 0.0 ? (double)A.dims[a] : 0.0) - o[a]) / d[a]);
                         }
-                        const long long kn = (long long)floor(te / A.step) - 1;
+                        // samples before kb lie a whole step inside; kb itself
+                        // is inside when the sampling path's own position test
+                        // (same arithmetic) puts it in the node and the volume
+                        const long long kb = (long long)floor(te / A.step);
+                        bool in = kb > k;
+                        if (in) {
+                            const double tk = (double)kb * A.step;
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                const double ua = o[a] + tk * d[a];
+                                in = in && ua >= 0.0 && ua < (double)A.dims[a] &&
+                                     ((((int)ua) ^ iu[a]) >> field(nd.nsh, a)) == 0;
+                            }
+                        }
+                        const long long kx = in ? kb + 1 : kb;  // first sample that may lie outside
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) lc[a] = (iu[a] >> field(nd.nsh, a)) << field(nd.nsh, a);
+                        lcd = dl;
                         if (all_empty) {
-                            skip_to = kn > k + 1 ? kn : k + 1;
+                            skip_to = kx > k + 1 ? kx : k + 1;
                             ++k;
                             skipped = true;
                         } else if constexpr (HOMOG) {
                             // render-and-skip: composited after the descent
-                            rs_end = kn;
+                            rs_end = kx;
                             rs_node = node;
                             rs_mask = hm;
                         }
@@ -699,18 +752,10 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                             hsg += al * gg;
                             hsb += al * bb;
                         }
-                        double tb = INFINITY;
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            if (d[a] == 0.0) continue;
-                            const double bound = d[a] > 0.0 ? (double)A.dims[a] : 0.0;
-                            tb = fmin(tb, (bound - o[a]) / d[a]);
-                        }
-                        // rs_end and the box's last sample lie a whole step
-                        // inside their boxes, so they are taken too; samples
-                        // from the next level threshold on are not
-                        long long end = (long long)floor(tb / A.step);
-                        end = rs_end + 1 < end ? rs_end + 1 : end;
+                        // samples before rs_end lie in the node and the
+                        // volume; those from the next level threshold on are
+                        // not taken
+                        long long end = rs_end;
                         if (adaptive && lod + 1 < L && (long long)s_lv[lod + 1].K < end) end = s_lv[lod + 1].K;
                         const long long rr = 1ll << rsh;
                         long long n = (end - k + rr - 1) / rr;
@@ -742,6 +787,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 cur_leaf = leaf;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) lc[a] = (iu[a] >> field(leafl.nsh, a)) << field(leafl.nsh, a);
+                lcd = D;
             }
             cur_lod = lod;
             ++st_visits;
