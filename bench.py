@@ -530,79 +530,88 @@ def adaptive_bench(scene, fl, frames, reps=3):
 
 def homogeneous_bench(frames=(0, 12), reps=7, W=1920, H=1080, haze=0.05):
     """Render-and-skip of nodes homogeneous for all channels
-    (RO_RENDER_HOMOGENEOUS) on a fully resident 4-channel 1024x1024x64 u16
-    cell volume whose leaf metadata are computed on the GPU from the level-0
-    bricks (exact, so the cell-free background has min == max == 0).
-    Channels 0 and 2 show a faint haze at the low values (value 0 is
-    visible), 1 and 3 are empty there, so background nodes are homogeneous
-    or empty in every channel.  Each orbit frame is rendered plain and with
-    the option, once untimed and then `reps` times: median kernel time from
-    HIP events, samples, brick reads, distinct bricks read, samples rendered
-    from homogeneous nodes, and the largest image difference (zero where
-    level 0 is read; a coarse level's interpolation may differ from the
-    node's value)."""
+    (RO_RENDER_HOMOGENEOUS) on two fully resident 4-channel 1024x1024x64
+    u16 volumes whose leaf metadata are computed on the GPU from the level-0
+    bricks (exact, so a constant region has min == max): the cell volume
+    (cells on an empty background) and constant boxes on an empty
+    background.  Channels 0 and 2 show a faint haze at the low values (value
+    0 is visible), 1 and 3 are empty there, so background nodes are
+    homogeneous or empty in every channel; box interiors are homogeneous.
+    Each orbit frame is rendered plain and with the option, once untimed and
+    then `reps` times: median kernel time from HIP events, samples, brick
+    reads, distinct bricks read, samples rendered from homogeneous nodes,
+    wave iterations, and the largest image difference (zero where level 0 is
+    read; a coarse level's interpolation may differ from the node's
+    value)."""
     import torch
     import synth
     from paper_2309_04393_amd import resoct
     from paper_2309_04393_amd.pipeline import GpuScene
-    vol = synth.CellVolume((1024, 1024, 64), 4, spacing=(1, 1, 4), n_levels=6, seed=2)
-    t = time.perf_counter()
-    n_all = resoct.Volume(vol.dims, vol.spacing, 4, 2, 32, vol.n_levels).brick_count()
-    scene = GpuScene(vol, 32, (16, 16, 4), 6, n_all, max_batch=4096, set_metadata=False)
-    for c in range(4):
-        scene.set_unknown(c)
-    ids = scene.all_ids()
-    scene.upload(0, ids)
-    scene.tree.update_residency()
-    torch.cuda.synchronize()
-    log(f"homogeneous leaves: {len(ids)} bricks resident ({time.perf_counter() - t:.1f} s)")
-    l0 = scene.all_ids(levels=[0])
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    scene.tree.leaf_metadata_from_bricks(l0)
-    b.record()
-    torch.cuda.synchronize()
-    out = {"workload": "4ch-1024x1024x64-u16, every brick resident, leaf metadata from the level-0 bricks",
-           "image": [W, H], "metadata_from_bricks_ms": a.elapsed_time(b), "level0_bricks": len(l0)}
-    chans = []
-    for c in range(4):
-        tf = synth.tf_hue(c / 4.0, 0.1)
-        if c % 2 == 0:
-            tf[:9] = tf[8]
-            tf[:9, 3] = haze
-        chans.append(dict(c=c, lo=0, hi=vol.n_levels - 1, W0=100 * 256, W1=2000 * 256, tf=tf))
-    cams = synth.orbit_path(vol.dims, vol.spacing, 24)
-    for cam in cams:
-        if cam["proj"] == "persp":
-            cam["tx"] = cam["ty"] * W / H
-    tf_dev = scene.tf_tensor(chans)
-    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
-    img = [torch.empty(W * H * 4, dtype=torch.float32, device="cuda") for _ in range(2)]
-    fno = 1
-    for f in frames:
-        row = {}
-        for k, (name, flags) in enumerate((("plain", 0), ("homogeneous", resoct.RENDER_HOMOGENEOUS))):
-            ms = []
-            for it in range(reps + 1):
-                stats.zero_()
-                fno += 1
-                a.record()
-                scene.render(fno, cams[f], W, H, 0.5, chans, tf_dev=tf_dev, out=img[k], stats=stats, flags=flags)
-                b.record()
-                torch.cuda.synchronize()
-                if it:  # the first render of each mode is untimed
-                    ms.append(a.elapsed_time(b))
-            st = stats.cpu().numpy()
-            _, nused = scene.cache.read_usage(fno)
-            scene.cache.read_requests(1 << 22)
-            row[name] = dict(ms=float(np.median(ms)), samples=int(st[0]), brick_reads=int(st[1]),
-                             bricks_read=int(nused), leaf_visits=int(st[3]), homogeneous_samples=int(st[6]))
-        row["speedup"] = row["plain"]["ms"] / row["homogeneous"]["ms"]
-        row["image_max_abs_diff"] = float((img[0] - img[1]).abs().max().item())
-        out[str(f)] = row
-        log(f"homogeneous leaves, frame {f}: {row}")
-    del scene
-    torch.cuda.empty_cache()
+    out = {"image": [W, H], "workloads": {}}
+    for wname, make, wins in (
+            ("4ch-1024x1024x64-u16 cells", lambda: synth.CellVolume((1024, 1024, 64), 4, spacing=(1, 1, 4),
+                                                                   n_levels=6, seed=2), (100, 2000)),
+            ("4ch-1024x1024x64-u16 constant boxes", lambda: synth.box_plateau_volume(), (50 * 256, 255 * 256))):
+        vol = make()
+        t = time.perf_counter()
+        n_all = resoct.Volume(vol.dims, vol.spacing, 4, 2, 32, vol.n_levels).brick_count()
+        scene = GpuScene(vol, 32, (16, 16, 4), 6, n_all, max_batch=4096, set_metadata=False)
+        for c in range(4):
+            scene.set_unknown(c)
+        ids = scene.all_ids()
+        scene.upload(0, ids)
+        scene.tree.update_residency()
+        torch.cuda.synchronize()
+        log(f"homogeneous leaves ({wname}): {len(ids)} bricks resident ({time.perf_counter() - t:.1f} s)")
+        l0 = scene.all_ids(levels=[0])
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        scene.tree.leaf_metadata_from_bricks(l0)
+        b.record()
+        torch.cuda.synchronize()
+        res = {"metadata_from_bricks_ms": a.elapsed_time(b), "level0_bricks": len(l0)}
+        chans = []
+        for c in range(4):
+            tf = synth.tf_hue(c / 4.0, 0.1)
+            if c % 2 == 0:
+                tf[:9] = tf[8]
+                tf[:9, 3] = haze
+            chans.append(dict(c=c, lo=0, hi=vol.n_levels - 1, W0=wins[0] * 256, W1=wins[1] * 256, tf=tf))
+        cams = synth.orbit_path(vol.dims, vol.spacing, 24)
+        for cam in cams:
+            if cam["proj"] == "persp":
+                cam["tx"] = cam["ty"] * W / H
+        tf_dev = scene.tf_tensor(chans)
+        stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+        img = [torch.empty(W * H * 4, dtype=torch.float32, device="cuda") for _ in range(2)]
+        fno = 1
+        for f in frames:
+            row = {}
+            for k, (name, flags) in enumerate((("plain", 0), ("homogeneous", resoct.RENDER_HOMOGENEOUS))):
+                ms = []
+                for it in range(reps + 1):
+                    stats.zero_()
+                    fno += 1
+                    a.record()
+                    scene.render(fno, cams[f], W, H, 0.5, chans, tf_dev=tf_dev, out=img[k], stats=stats,
+                                 flags=flags)
+                    b.record()
+                    torch.cuda.synchronize()
+                    if it:  # the first render of each mode is untimed
+                        ms.append(a.elapsed_time(b))
+                st = stats.cpu().numpy()
+                _, nused = scene.cache.read_usage(fno)
+                scene.cache.read_requests(1 << 22)
+                row[name] = dict(ms=float(np.median(ms)), samples=int(st[0]), brick_reads=int(st[1]),
+                                 bricks_read=int(nused), leaf_visits=int(st[3]), wave_iterations=int(st[5]),
+                                 homogeneous_samples=int(st[6]))
+            row["speedup"] = row["plain"]["ms"] / row["homogeneous"]["ms"]
+            row["image_max_abs_diff"] = float((img[0] - img[1]).abs().max().item())
+            res[str(f)] = row
+            log(f"homogeneous leaves ({wname}), frame {f}: {row}")
+        out["workloads"][wname] = res
+        del scene
+        torch.cuda.empty_cache()
     return out
 
 

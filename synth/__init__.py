@@ -474,6 +474,24 @@ def plateau_volume(n_channels=2, seed=5, dims=(64, 64, 64), n_levels=3):
     return ArrayVolume(out, 8, (1, 1, 1), n_levels)
 
 
+def box_plateau_volume(dims=(1024, 1024, 64), n_channels=4, seed=6, n_boxes=24, spacing=(1, 1, 4), n_levels=6):
+    """u16 volume of constant-valued axis-aligned boxes on a zero background:
+    per channel c, box i holds (v_i + 17 c) * 256 (later boxes over earlier
+    ones).  The background and the box interiors are homogeneous in every
+    channel, the leaves on box faces are not."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    out = [np.zeros((nz, ny, nx), np.uint16) for _ in range(n_channels)]
+    for _ in range(n_boxes):
+        ext = (int(rng.integers(nx // 16, nx // 4)), int(rng.integers(ny // 16, ny // 4)),
+               int(rng.integers(max(1, nz // 4), max(2, nz // 2))))
+        lo = [int(rng.integers(0, dims[a] - ext[a] + 1)) for a in range(3)]
+        v = int(rng.integers(60, 200))
+        for c in range(n_channels):
+            out[c][lo[2]:lo[2] + ext[2], lo[1]:lo[1] + ext[1], lo[0]:lo[0] + ext[0]] = (v + 17 * c) * 256
+    return ArrayVolume(out, 16, spacing, n_levels)
+
+
 def config1_volume(seed=1):
     """64^3 u8, 40 blobs, noise 0.02, 3 levels."""
     return BlobVolume((64, 64, 64), n_channels=1, bits=8, n_levels=3, seed=seed)
