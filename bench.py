@@ -82,7 +82,7 @@ def _csv_rows(d, suffix):
     return rows
 
 
-def profile_summary(trace_dir, fetch_dir, write_dir, last, workload, kernel="k_render<16, 2, false, 34, false>"):
+def profile_summary(trace_dir, fetch_dir, write_dir, last, workload, kernel="k_render<16, 2, false, 34, 0>"):
     """Markdown summary of rocprofv3 runs of the headline frame loop: mean
     duration of the last `last` dispatches of the headline kernel (the timed
     pass; the untimed pass A and the warm-up frames come before it) from the

@@ -49,7 +49,7 @@ namespace ro {
 // Persistent grid (one workgroup per CU) whose waves take 8 x 8-pixel blocks
 // from a device counter independently of each other, so a CU never waits
 // for the slowest wave of a workgroup before taking new work.
-template <int NV, int BPV, bool AOV, int EC, bool HOMOG>
+template <int NV, int BPV, bool AOV, int EC, int EXT>
 __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(kRenderLanes / 256)))
     k_render(const RenderArgs A, uint32_t *counter, uint32_t n_blocks, uint32_t tiles_x) {
     extern __shared__ float4 s_tf[];  // [NV][256] tables, then [NV][kRenderLanes] slot words
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
     q.min_idle = RO_MIN_IDLE;
     uint32_t st[7] = {0, 0, 0, 0, 0, 0, 0};
     const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
-    render_rays<NV, BPV, AOV, EC, EC == 0, HOMOG>(A, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
+    render_rays<NV, BPV, AOV, EC, EC == 0, EXT>(A, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
     if (A.stats) {
         // every lane of the workgroup is here: reduce over the wave, one atomic per wave
 #pragma unroll
@@ -91,32 +91,34 @@ struct QueueLaunch {
     uint32_t n_blocks, tiles_x;
 };
 
-template <int NV, int BPV, bool AOV, int EC, bool HOMOG = false>
+template <int NV, int BPV, bool AOV, int EC, int EXT = 0>
 static hipError_t launch_one(const RenderArgs &A, const QueueLaunch &Q, hipStream_t s) {
-    const size_t lds = render_lds_bytes(NV, HOMOG);
-    hipError_t e = hipFuncSetAttribute((const void *)k_render<NV, BPV, AOV, EC, HOMOG>,
+    const size_t lds = render_lds_bytes(NV, (EXT & 1) != 0);
+    hipError_t e = hipFuncSetAttribute((const void *)k_render<NV, BPV, AOV, EC, EXT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_render<NV, BPV, AOV, EC, HOMOG>), Q.grid, dim3(kRenderLanes), lds, s, A, Q.counter, Q.n_blocks,
+    hipLaunchKernelGGL((k_render<NV, BPV, AOV, EC, EXT>), Q.grid, dim3(kRenderLanes), lds, s, A, Q.counter, Q.n_blocks,
                        Q.tiles_x);
     return hipGetLastError();
 }
 
 // Compile-time brick edges: 32^3 and 16^3 bricks with their halo (the AOV
 // diagnostic output and the LOD-adaptive step take the generic kernel).
-// Render-and-skip of homogeneous nodes has instantiations of its own, so the
-// kernels that do not take it carry none of its code.
+// Render-and-skip of homogeneous nodes (EXT bit 0) and per-channel sampling
+// rates (EXT bit 1) have instantiations of their own, so the kernels that do
+// not take them carry none of their code.
 template <int NV, int BPV>
 static hipError_t launch_nv(const RenderArgs &A, bool aov, const QueueLaunch &Q, hipStream_t s) {
-    if (aov) return launch_one<NV, BPV, true, 0, true>(A, Q, s);
+    if (aov) return launch_one<NV, BPV, true, 0, 3>(A, Q, s);
     if (A.flags & RO_RENDER_ADAPTIVE_STEP) {
-        if (A.flags & RO_RENDER_HOMOGENEOUS) return launch_one<NV, BPV, false, 0, true>(A, Q, s);
+        if (A.flags & RO_RENDER_HOMOGENEOUS) return launch_one<NV, BPV, false, 0, 1>(A, Q, s);
+        if (A.flags & RO_RENDER_CHANNEL_RATES) return launch_one<NV, BPV, false, 0, 2>(A, Q, s);
         return launch_one<NV, BPV, false, 0>(A, Q, s);
     }
     if (A.flags & RO_RENDER_HOMOGENEOUS) {
-        if (A.E == 34) return launch_one<NV, BPV, false, 34, true>(A, Q, s);
-        if (A.E == 18) return launch_one<NV, BPV, false, 18, true>(A, Q, s);
-        return launch_one<NV, BPV, false, 0, true>(A, Q, s);
+        if (A.E == 34) return launch_one<NV, BPV, false, 34, 1>(A, Q, s);
+        if (A.E == 18) return launch_one<NV, BPV, false, 18, 1>(A, Q, s);
+        return launch_one<NV, BPV, false, 0, 1>(A, Q, s);
     }
     if (A.E == 34) return launch_one<NV, BPV, false, 34>(A, Q, s);
     if (A.E == 18) return launch_one<NV, BPV, false, 18>(A, Q, s);

@@ -306,13 +306,15 @@ __host__ __device__ constexpr size_t slot_bytes(int e, int bpv) {
 
 // EC: the brick edge with halo known at compile time (0: read from A).  A
 // constant edge turns the four gather offsets into instruction immediates.
-// ADAPT / HOMOG: whether the LOD-adaptive step / render-and-skip of nodes
-// homogeneous for all channels are compiled in (frames that ask for them go
-// to a kernel that has them).
-template <int NV, int BPV, bool AOV, int EC, bool ADAPT, bool HOMOG, class Source>
+// ADAPT: whether the LOD-adaptive step is compiled in; EXT: bit 0
+// render-and-skip of nodes homogeneous for all channels, bit 1 per-channel
+// sampling rates (frames that ask for them go to a kernel that has them).
+template <int NV, int BPV, bool AOV, int EC, bool ADAPT, int EXT, class Source>
 __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, const float4 *s_tf,
                                             const ChanLds *s_ch, const uint32_t *s_runs, const LevLds *s_lv,
                                             const NodeLds *s_nd, uint32_t stats[7], LdsSlots slot) {
+    constexpr bool HOMOG = (EXT & 1) != 0;
+    constexpr bool RATES = ADAPT && (EXT & 2) != 0;
     const int nvis = A.nvis;
     const int D = A.depth;
     const int L = A.L;
@@ -326,7 +328,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     const bool homog = HOMOG && (A.flags & RO_RENDER_HOMOGENEOUS) != 0;
     // per-channel sampling rates (with the adaptive step): a channel takes part
     // only in samples k that are multiples of its own level's x factor
-    const bool rates = ADAPT && adaptive && (A.flags & RO_RENDER_CHANNEL_RATES) != 0;
+    const bool rates = RATES && adaptive && (A.flags & RO_RENDER_CHANNEL_RATES) != 0;
     // traversal depth from the step (with the adaptive step): emptiness and
     // homogeneity are decided at the node of depth dd of the step's level
     const bool tdepth = ADAPT && adaptive && (A.flags & RO_RENDER_TRAVERSAL_DEPTH) != 0;

@@ -66,7 +66,7 @@ __device__ __forceinline__ void serve_item(const RenderArgs &sA, uint32_t seg, u
     q.min_idle = 64;
     uint32_t st[7] = {0, 0, 0, 0, 0, 0, 0};
     const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
-    render_rays<NV, BPV, false, EC, true, false>(sA, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
+    render_rays<NV, BPV, false, EC, true, 0>(sA, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
     if (sA.stats) {
 #pragma unroll
         for (int j = 0; j < 7; ++j) {

@@ -251,14 +251,23 @@ class Cache:
                                      _np_ptr(flags), _stream(stream)), "ro_stream_bricks")
         return flags[:n]
 
+    def _pinned(self, name: str, n: int) -> np.ndarray:
+        """A reusable page-locked uint32 host buffer of at least n entries (the
+        device-to-host copies of the readbacks then need no staging)."""
+        buf = getattr(self, name, None)
+        if buf is None or buf.numel() < n:
+            buf = torch.empty(max(n, 1), dtype=torch.int32, pin_memory=True)
+            setattr(self, name, buf)
+        return buf.numpy().view(np.uint32)
+
     def read_requests(self, cap: int, stream=None):
-        ids = np.zeros(max(cap, 1), np.uint32)
-        cnt = np.zeros(max(cap, 1), np.uint32)
+        ids = self._pinned("_rq_ids", cap)
+        cnt = self._pinned("_rq_cnt", cap)
         nu, tot = c_u32(), c_u64()
         _check(_lib.ro_read_requests(self.h, cap, _np_ptr(ids), _np_ptr(cnt), ctypes.byref(nu),
                                      ctypes.byref(tot), _stream(stream)), "ro_read_requests")
         k = min(cap, nu.value)
-        return ids[:k], cnt[:k], int(nu.value), int(tot.value)
+        return ids[:k].copy(), cnt[:k].copy(), int(nu.value), int(tot.value)
 
     def read_requests_noalloc(self, cap: int, stream=None):
         """ro_read_requests_noalloc: the same readback with the library's fixed work space."""
@@ -272,11 +281,11 @@ class Cache:
 
     def read_usage(self, frame: int, cap: int = None, stream=None):
         cap = self.n_slots if cap is None else cap
-        out = np.zeros(max(cap, 1), np.uint32)
+        out = self._pinned("_us_out", cap)
         n = c_u32()
         _check(_lib.ro_read_usage(self.h, frame, cap, _np_ptr(out), ctypes.byref(n), _stream(stream)),
                "ro_read_usage")
-        return out[:min(cap, n.value)], int(n.value)
+        return out[:min(cap, n.value)].copy(), int(n.value)
 
     def save_state(self) -> np.ndarray:
         n = c_sz()
