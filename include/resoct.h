@@ -213,12 +213,28 @@ ro_status ro_restore(ro_octree *t, const void *host_blob, size_t size, void *str
  * out of range.  Queues one kernel; the host mirrors change at once. */
 ro_status ro_cache_evict_channel(ro_cache *c, uint32_t channel, void *stream);
 
+/* Channel map (Sec. 5.2: the octree and page tables reference m of the data
+ * server's channels at a time; a cache channel can be given another data
+ * channel at run time).  Host state of the cache: cache channel c shows
+ * source channel map[c], the identity at create.  The GPU works in cache
+ * channels only; the map names the data behind them, so requests read back
+ * as brick IDs (cache channel, level, brick) are fetched from the server
+ * through ro_cache_source_bricks.  Set it with the exchange
+ * (ro_cache_evict_channel).  RO_E_ARG for a cache channel >= m. */
+ro_status ro_cache_set_channel_map(ro_cache *c, uint32_t cache_channel, uint32_t source_channel);
+/* map[m]: the source channel of every cache channel. */
+ro_status ro_cache_get_channel_map(const ro_cache *c, uint32_t *map);
+/* For each of ids[n]: out[5 i ..] = (source channel, level, bx, by, bz), the
+ * brick as the data server names it.  RO_E_ARG, with nothing written, if an
+ * ID is out of range. */
+ro_status ro_cache_source_bricks(const ro_cache *c, uint32_t n, const uint32_t *ids, uint32_t *out);
+
 /* Copy of the host mirror of the page table: brick index -> slot
  * (0xFFFFFFFF when not resident), `count` entries from ro_volume_brick_count. */
 ro_status ro_cache_page_table_host(const ro_cache *c, uint32_t *out, uint64_t count);
 
 /* Host-side state of a cache: page-table and slot-map mirrors, bricks
- * awaiting a residency update, upload counter.  Together with copies of the
+ * awaiting a residency update, channel map, upload counter.  Together with copies of the
  * caller-owned device buffers (page table, counters, slot map, stamps, seqs,
  * slots, node masks and metadata) it is a complete checkpoint: save, later
  * copy the device buffers back and load, and the cache continues exactly as

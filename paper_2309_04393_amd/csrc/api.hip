@@ -234,6 +234,8 @@ extern "C" ro_status ro_cache_create(const ro_volume *v, const ro_cache_desc *d,
     try {
         c->pt_host.assign(v->g.total, kInvalid);
         c->slot_host.assign(d->n_slots, kInvalid);
+        c->chmap.resize(v->g.m);
+        for (int j = 0; j < v->g.m; ++j) c->chmap[j] = (uint32_t)j;
     } catch (...) {
         delete c;
         RO_CHECK(false, RO_E_NOMEM, "out of host memory");
@@ -272,16 +274,49 @@ extern "C" ro_status ro_cache_page_table_host(const ro_cache *c, uint32_t *out, 
     return RO_OK;
 }
 
-// Checkpoint blob: header, then the page-table mirror, slot mirror and dirty list.
+// Checkpoint blob: header, then the page-table mirror, slot mirror, dirty
+// list and channel map.
 struct StateHeader {
     uint64_t magic, total, slots, dirty;
-    uint32_t seq_next, pad;
+    uint32_t seq_next, channels;
 };
-static const uint64_t kStateMagic = 0x31455441545352ull;  // "RSTATE1"
+static const uint64_t kStateMagic = 0x32455441545352ull;  // "RSTATE2"
 
 extern "C" ro_status ro_cache_state_size(const ro_cache *c, size_t *bytes) {
     RO_CHECK(c && bytes, RO_E_ARG, "null argument");
-    *bytes = sizeof(StateHeader) + 4 * (c->pt_host.size() + c->slot_host.size() + c->dirty.size());
+    *bytes = sizeof(StateHeader) + 4 * (c->pt_host.size() + c->slot_host.size() + c->dirty.size() + c->chmap.size());
+    return RO_OK;
+}
+
+extern "C" ro_status ro_cache_set_channel_map(ro_cache *c, uint32_t cache_channel, uint32_t source_channel) {
+    RO_CHECK(c, RO_E_ARG, "null cache");
+    RO_CHECK(cache_channel < c->chmap.size(), RO_E_ARG, "cache channel %u out of range", cache_channel);
+    c->chmap[cache_channel] = source_channel;
+    return RO_OK;
+}
+
+extern "C" ro_status ro_cache_get_channel_map(const ro_cache *c, uint32_t *map) {
+    RO_CHECK(c && map, RO_E_ARG, "null argument");
+    memcpy(map, c->chmap.data(), 4 * c->chmap.size());
+    return RO_OK;
+}
+
+extern "C" ro_status ro_cache_source_bricks(const ro_cache *c, uint32_t n, const uint32_t *ids, uint32_t *out) {
+    RO_CHECK(c && (n == 0 || (ids && out)), RO_E_ARG, "null argument");
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t cc, ll, bb[3];
+        RO_CHECK(decode_id(c->vol->g, ids[i], &cc, &ll, bb), RO_E_ARG, "brick ID 0x%08x out of range", ids[i]);
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t cc, ll, bb[3];
+        decode_id(c->vol->g, ids[i], &cc, &ll, bb);
+        uint32_t *o = out + 5 * (size_t)i;
+        o[0] = c->chmap[cc];
+        o[1] = ll;
+        o[2] = bb[0];
+        o[3] = bb[1];
+        o[4] = bb[2];
+    }
     return RO_OK;
 }
 
@@ -290,7 +325,8 @@ extern "C" ro_status ro_cache_save_state(const ro_cache *c, void *host, size_t c
     ro_status st = ro_cache_state_size(c, &need);
     if (st) return st;
     RO_CHECK(host && cap >= need, RO_E_ARG, "buffer of %zu bytes needed", need);
-    StateHeader hd = {kStateMagic, c->pt_host.size(), c->slot_host.size(), c->dirty.size(), c->seq_next, 0};
+    StateHeader hd = {kStateMagic, c->pt_host.size(), c->slot_host.size(), c->dirty.size(), c->seq_next,
+                      (uint32_t)c->chmap.size()};
     uint8_t *p = (uint8_t *)host;
     memcpy(p, &hd, sizeof(hd));
     p += sizeof(hd);
@@ -299,6 +335,8 @@ extern "C" ro_status ro_cache_save_state(const ro_cache *c, void *host, size_t c
     memcpy(p, c->slot_host.data(), 4 * c->slot_host.size());
     p += 4 * c->slot_host.size();
     if (!c->dirty.empty()) memcpy(p, c->dirty.data(), 4 * c->dirty.size());
+    p += 4 * c->dirty.size();
+    memcpy(p, c->chmap.data(), 4 * c->chmap.size());
     return RO_OK;
 }
 
@@ -307,7 +345,7 @@ extern "C" ro_status ro_cache_load_state(ro_cache *c, const void *host, size_t s
     StateHeader hd;
     memcpy(&hd, host, sizeof(hd));
     RO_CHECK(hd.magic == kStateMagic && hd.total == c->pt_host.size() && hd.slots == c->slot_host.size() &&
-                 size == sizeof(hd) + 4 * (hd.total + hd.slots + hd.dirty),
+                 hd.channels == c->chmap.size() && size == sizeof(hd) + 4 * (hd.total + hd.slots + hd.dirty + hd.channels),
              RO_E_ARG, "state blob does not match this cache");
     const uint8_t *p = (const uint8_t *)host + sizeof(hd);
     try {
@@ -319,6 +357,7 @@ extern "C" ro_status ro_cache_load_state(ro_cache *c, const void *host, size_t s
     }
     memcpy(c->pt_host.data(), p, 4 * hd.total);
     memcpy(c->slot_host.data(), p + 4 * hd.total, 4 * hd.slots);
+    memcpy(c->chmap.data(), p + 4 * (hd.total + hd.slots + hd.dirty), 4 * (size_t)hd.channels);
     c->seq_next = hd.seq_next;
     return RO_OK;
 }
@@ -606,7 +645,8 @@ extern "C" ro_status ro_restore(ro_octree *t, const void *host_blob, size_t size
     StateHeader sh;
     memcpy(&sh, i, sizeof(sh));
     RO_CHECK(sh.magic == kStateMagic && sh.total == c->pt_host.size() && sh.slots == c->slot_host.size() &&
-                 hd.host_bytes == sizeof(sh) + 4 * (sh.total + sh.slots + sh.dirty),
+                 sh.channels == c->chmap.size() &&
+                 hd.host_bytes == sizeof(sh) + 4 * (sh.total + sh.slots + sh.dirty + sh.channels),
              RO_E_ARG, "snapshot blob's cache state does not match this cache");
     // device arrays, then the host mirrors
     hipStream_t s = (hipStream_t)stream;

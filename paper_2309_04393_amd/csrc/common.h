@@ -119,6 +119,7 @@ struct ro_cache {
     std::vector<uint32_t> pt_host;     // brick -> slot mirror
     std::vector<uint32_t> slot_host;   // slot -> brick mirror
     std::vector<uint32_t> dirty;       // bricks inserted / evicted since the last residency update
+    std::vector<uint32_t> chmap;       // cache channel -> source channel (Sec. 5.2)
     uint32_t seq_next;
 };
 

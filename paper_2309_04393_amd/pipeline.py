@@ -21,9 +21,6 @@ class GpuScene:
         self.device = device
         m = src.n_channels if cache_channels is None else int(cache_channels)
         assert 1 <= m <= src.n_channels
-        # cache channel c holds the source's channel channel_map[c] (Sec. 5.2:
-        # the octree and page tables reference m of the n channels at a time)
-        self.channel_map = list(range(m))
         self.vol = resoct.Volume(src.dims, src.spacing, m, 1 if src.bits == 8 else 2,
                                  brick, src.n_levels)
         self.cache = resoct.Cache(self.vol, n_slots, max_batch, device=device)
@@ -36,6 +33,13 @@ class GpuScene:
         if set_metadata:
             for c in range(m):
                 self.set_metadata(c, src.leaf_minmax(self.channel_map[c], self.leaf, self.tree.leaf_grid))
+
+    @property
+    def channel_map(self) -> list:
+        """Cache channel c holds the source's channel channel_map[c] (Sec. 5.2:
+        the octree and page tables reference m of the n channels at a time);
+        the map is the cache's (the library's host state)."""
+        return self.cache.channel_map()
 
     def set_metadata(self, c, leaf_mm: np.ndarray):
         t = torch.from_numpy(np.ascontiguousarray(leaf_mm, dtype=np.uint16).reshape(-1).view(np.int16))
@@ -57,7 +61,7 @@ class GpuScene:
         and the residency masks are updated; the new bricks arrive through
         the usual request-driven uploads."""
         self.cache.evict_channel(c)
-        self.channel_map[c] = int(src_channel)
+        self.cache.set_channel_map(c, int(src_channel))
         if metadata == "server":
             self.set_metadata(c, self.src.leaf_minmax(int(src_channel), self.leaf, self.tree.leaf_grid))
         else:
@@ -84,7 +88,7 @@ class GpuScene:
         host = np.zeros((max(n, 1), stride), np.uint8)
         nbytes = self.E ** 3 * (1 if self.np_dtype == np.uint8 else 2)
         # (source channel, level, brick) of each ID
-        dec = [(self.channel_map[c], l, b) for c, l, b in (self.vol.decode(int(i)) for i in ids)]
+        dec = [(int(r[0]), int(r[1]), (int(r[2]), int(r[3]), int(r[4]))) for r in self.cache.source_bricks(ids)]
         if hasattr(self.src, "bricks_multi"):
             # one generator pass per brick position serves every channel there
             groups = {}

@@ -103,6 +103,9 @@ _sig("ro_read_requests", c_i32, [c_vp, c_u32, c_vp, c_vp, _P(c_u32), _P(c_u64), 
 _sig("ro_read_requests_noalloc", c_i32, [c_vp, c_u32, c_vp, c_vp, _P(c_u32), _P(c_u64), c_vp])
 _sig("ro_read_usage", c_i32, [c_vp, c_u32, c_u32, c_vp, _P(c_u32), c_vp])
 _sig("ro_cache_evict_channel", c_i32, [c_vp, c_u32, c_vp])
+_sig("ro_cache_set_channel_map", c_i32, [c_vp, c_u32, c_u32])
+_sig("ro_cache_get_channel_map", c_i32, [c_vp, c_vp])
+_sig("ro_cache_source_bricks", c_i32, [c_vp, c_u32, c_vp, c_vp])
 _sig("ro_cache_page_table_host", c_i32, [c_vp, c_vp, c_u64])
 _sig("ro_cache_state_size", c_i32, [c_vp, _P(c_sz)])
 _sig("ro_cache_save_state", c_i32, [c_vp, c_vp, c_sz])
@@ -300,6 +303,21 @@ class Cache:
 
     def evict_channel(self, channel: int, stream=None):
         _check(_lib.ro_cache_evict_channel(self.h, channel, _stream(stream)), "ro_cache_evict_channel")
+
+    def set_channel_map(self, cache_channel: int, source_channel: int):
+        _check(_lib.ro_cache_set_channel_map(self.h, cache_channel, source_channel), "ro_cache_set_channel_map")
+
+    def channel_map(self) -> list:
+        out = np.zeros(self.vol.n_channels, np.uint32)
+        _check(_lib.ro_cache_get_channel_map(self.h, _np_ptr(out)), "ro_cache_get_channel_map")
+        return [int(x) for x in out]
+
+    def source_bricks(self, ids) -> np.ndarray:
+        """[n][5] (source channel, level, bx, by, bz) of brick IDs."""
+        ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
+        out = np.zeros((max(len(ids), 1), 5), np.uint32)
+        _check(_lib.ro_cache_source_bricks(self.h, len(ids), _np_ptr(ids), _np_ptr(out)), "ro_cache_source_bricks")
+        return out[:len(ids)]
 
     def page_table_host(self) -> np.ndarray:
         out = np.zeros(self.n_bricks, np.uint32)

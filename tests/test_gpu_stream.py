@@ -352,11 +352,27 @@ def test_channel_exchange():
     assert np.array_equal(g.tree.masks(), oracle.masks(V, sim.res_slot))
     ids, cnt = frame(2, "exchange-no-bricks")  # channel 1 contributes nothing yet and requests its bricks
     assert np.any((ids >> 24) // src.n_levels == 1)
+    # the library's channel map names the data behind the requested IDs
+    assert g.channel_map == [0, 4, 2]
+    sb = g.cache.source_bricks(ids)
+    for i, r in zip(ids, sb):
+        c, l, b = g.vol.decode(int(i))
+        assert tuple(int(x) for x in r) == ([0, 4, 2][c], l, *b)
+    with pytest.raises(resoct.ResoctError):
+        g.cache.set_channel_map(3, 0)
+    with pytest.raises(resoct.ResoctError):
+        g.cache.source_bricks(np.array([0xFFFFFFFF], np.uint32))
     order = np.lexsort((ids, -cnt.astype(np.int64)))
     upload(3, ids[order][:200])
     g.tree.update_residency()
     assert np.array_equal(g.tree.masks(), oracle.masks(V, sim.res_slot))
     frame(4, "exchange-after")
+    # the map is part of a snapshot
+    blob = g.tree.snapshot(slots=False)
+    g.cache.set_channel_map(1, 1)
+    assert g.channel_map == [0, 1, 2]
+    g.tree.restore(blob)
+    assert g.channel_map == [0, 4, 2]
 
 
 def test_leaf_metadata_from_u8_bricks():
