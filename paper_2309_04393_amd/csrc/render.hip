@@ -24,9 +24,9 @@ namespace ro {
 
 // Workgroups of kRenderLanes lanes (768: 3 waves per SIMD, up to 168 VGPRs),
 // one per CU: one copy of the frame's LDS tables plus the per-lane slot
-// words.  The 16-channel instantiations keep 8 to 40 bytes per lane in
-// scratch (12 for 32^3 bricks without the options), some 8-channel ones 8
-// to 12, the others none.  1024 lanes (4 waves per SIMD, 128 VGPRs) spill
+// words.  The 16-channel instantiations for 32^3 and 16^3 bricks without
+// the options keep nothing in scratch; the other 16-channel ones and some
+// 8-channel ones 8 to 40 bytes per lane.  1024 lanes (4 waves per SIMD, 128 VGPRs) spill
 // more and measured 1-10 % slower, 512 lanes 35 % slower.
 
 // Lanes refill only when the whole wave is idle: a wave then takes a whole
@@ -52,7 +52,7 @@ namespace ro {
 template <int NV, int BPV, bool AOV, int EC, int EXT>
 __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(kRenderLanes / 256)))
     k_render(const RenderArgs A, uint32_t *counter, uint32_t n_blocks, uint32_t tiles_x) {
-    extern __shared__ float4 s_tf[];  // [NV][256] tables, then [NV][kRenderLanes] slot words
+    extern __shared__ float4 s_tf[];  // [NV][kTfStride] tables, then [NV][kRenderLanes] slot words
     __shared__ ChanLds s_ch[NV];
     __shared__ uint32_t s_runs[NV * kMaxRuns];
     __shared__ LevLds s_lv[kMaxL];
@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_
     q.H = A.H;
     q.min_idle = RO_MIN_IDLE;
     uint32_t st[7] = {0, 0, 0, 0, 0, 0, 0};
-    const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
+    const LdsSlots sl{(uint32_t *)(s_tf + kTfStride * NV) + threadIdx.x, (uint32_t)kRenderLanes};
     render_rays<NV, BPV, AOV, EC, EC == 0, EXT>(A, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
     if (A.stats) {
         // every lane of the workgroup is here: reduce over the wave, one atomic per wave

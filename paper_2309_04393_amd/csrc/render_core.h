@@ -107,19 +107,21 @@ __device__ __forceinline__ bool range_empty(uint32_t mm, const uint32_t *runs, i
     return false;
 }
 
+// A channel's transfer-function table in LDS: its 256 entries and a copy of
+// the last, so the interpolation's upper entry needs no clamp.
+constexpr int kTfStride = 257;
+
 // Transfer function of a visible channel at raw value v: window, table
-// position, linear interpolation of the LDS table (tf = the channel's 256
-// entries).
+// position, linear interpolation of the LDS table (tf = the channel's
+// entries; at the top end the weight of the copy is zero).
 __device__ __forceinline__ void classify(float v, const ChanLds &ch, const float4 *tf, float &al, float &r, float &g,
                                          float &b) {
     float x = (v - ch.w0) * ch.iw;
     x = fminf(fmaxf(x, 0.0f), 1.0f);
     const float p = x * 255.0f;
-    int e = (int)p;
-    e = e > 255 ? 255 : e;
-    const int e1i = e + (e < 255 ? 1 : 0);
+    const int e = (int)p;  // 0 .. 255
     const float f = p - (float)e;
-    const float4 ta = tf[e], tb = tf[e1i];
+    const float4 ta = tf[e], tb = tf[e + 1];
     al = ta.w + (tb.w - ta.w) * f;
     r = ta.x + (tb.x - ta.x) * f;
     g = ta.y + (tb.y - ta.y) * f;
@@ -183,7 +185,7 @@ struct HomLane {
 // word per lane and visible channel, then (kernels with render-and-skip)
 // one HomLane per lane.
 __host__ __device__ constexpr size_t render_lds_bytes(int nv, bool homog = false) {
-    return (size_t)nv * 256 * 16 + (size_t)nv * kRenderLanes * 4 + (homog ? kRenderLanes * sizeof(HomLane) : 0);
+    return (size_t)nv * kTfStride * 16 + (size_t)nv * kRenderLanes * 4 + (homog ? kRenderLanes * sizeof(HomLane) : 0);
 }
 
 // Slot of each visible channel for a lane's current visit, kept in LDS (one
@@ -360,7 +362,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
     // sample per wave iteration, until skip_to (its state in LDS)
     bool hom_on = false;
     HomLane *hl = nullptr;
-    if constexpr (HOMOG) hl = (HomLane *)((uint32_t *)(s_tf + 256 * NV) + NV * kRenderLanes) + threadIdx.x;
+    if constexpr (HOMOG) hl = (HomLane *)((uint32_t *)(s_tf + kTfStride * NV) + NV * kRenderLanes) + threadIdx.x;
 
     // ray set-up in L0 voxel units, box interval, first sample index
     auto start = [&](int x, int y, bool valid) {
@@ -747,7 +749,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                             if (!((rs_mask >> j) & 1u)) continue;
                             const ChanLds ch = s_ch[j];
                             float al, r, gg, bb;
-                            classify((float)(rm[ch.c] & 0xFFFFu), ch, s_tf + j * 256, al, r, gg, bb);
+                            classify((float)(rm[ch.c] & 0xFFFFu), ch, s_tf + j * kTfStride, al, r, gg, bb);
                             hp *= 1.0f - al;
                             hsa += al;
                             hsr += al * r;
@@ -981,6 +983,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
             }
         }
         st_nonempty += __popc(vismask & ~emask & part);
+        st_reads += __popc(have & part);  // the channels gathered below (those with a slot)
         // ---- sample every visible channel
         // In-brick coordinates depend only on the level a channel samples
         // (bricks of one level share their grid), so they are computed once
@@ -1063,8 +1066,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 const float e1 = c01 + (c11 - c01) * f1;
                 const float v = e0 + (e1 - e0) * f2;
                 float al, r, gg, bb;
-                classify(v, s_ch[j], s_tf + j * 256, al, r, gg, bb);
-                ++st_reads;
+                classify(v, s_ch[j], s_tf + j * kTfStride, al, r, gg, bb);
                 if (rates) {
                     // the channel stands for r_c base steps: transparency
                     // (1 - alpha)^r_c, colour weight r_c alpha
@@ -1140,7 +1142,10 @@ template <int NV>
 __device__ __forceinline__ void stage_frame(const RenderArgs &A, float4 *s_tf, ChanLds *s_ch, uint32_t *s_runs,
                                             LevLds *s_lv, NodeLds *s_nd) {
     const int nvis = A.nvis;
-    for (int i = threadIdx.x; i < nvis * 256; i += blockDim.x) s_tf[i] = A.tf[i];
+    for (int i = threadIdx.x; i < nvis * kTfStride; i += blockDim.x) {
+        const int t = i / kTfStride, e = i - t * kTfStride;
+        s_tf[i] = A.tf[t * 256 + (e < 256 ? e : 255)];
+    }
     const unsigned t = threadIdx.x;
     if (t < (unsigned)A.L) {
         LevLds lv;
@@ -1169,7 +1174,7 @@ __device__ __forceinline__ void stage_frame(const RenderArgs &A, float4 *s_tf, C
         ch.hi = A.hi[t];
         ch.w0 = A.w0[t];
         ch.iw = A.iw[t];
-        ch.nruns = build_runs(s_tf + t * 256, A.W0[t], A.W1[t], s_runs + t * kMaxRuns);
+        ch.nruns = build_runs(s_tf + t * kTfStride, A.W0[t], A.W1[t], s_runs + t * kMaxRuns);
         const uint32_t r0 = s_runs[t * kMaxRuns];
         ch.ehi = (ch.nruns == 1 && (r0 & 0xFFFFu) == 0) ? (r0 >> 16) : 0xFFFFFFFFu;
         ch.single = 0;

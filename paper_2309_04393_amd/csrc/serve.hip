@@ -65,7 +65,7 @@ __device__ __forceinline__ void serve_item(const RenderArgs &sA, uint32_t seg, u
     q.H = sA.H;
     q.min_idle = 64;
     uint32_t st[7] = {0, 0, 0, 0, 0, 0, 0};
-    const LdsSlots sl{(uint32_t *)(s_tf + 256 * NV) + threadIdx.x, (uint32_t)kRenderLanes};
+    const LdsSlots sl{(uint32_t *)(s_tf + kTfStride * NV) + threadIdx.x, (uint32_t)kRenderLanes};
     render_rays<NV, BPV, false, EC, true, 0>(sA, q, s_tf, s_ch, s_runs, s_lv, s_nd, st, sl);
     if (sA.stats) {
 #pragma unroll
@@ -84,7 +84,7 @@ template <int NV, int BPV, int EC>
 __global__ void __launch_bounds__(kRenderLanes) __attribute__((amdgpu_waves_per_eu(kRenderLanes / 256)))
     k_serve(const ServeHeader *__restrict__ hdr, const RenderArgs *__restrict__ descs,
             const uint32_t *__restrict__ segs, uint32_t *__restrict__ queue) {
-    extern __shared__ float4 s_tf[];  // [NV][256] tables, then [NV][kRenderLanes] slot words
+    extern __shared__ float4 s_tf[];  // [NV][kTfStride] tables, then [NV][kRenderLanes] slot words
     __shared__ RenderArgs sA;
     __shared__ ChanLds s_ch[NV];
     __shared__ uint32_t s_runs[NV * kMaxRuns];
