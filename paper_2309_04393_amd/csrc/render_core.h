@@ -1022,16 +1022,31 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         // not live across the channels.
         auto sample_channels = [&](auto uni_c) {
             constexpr bool UNI = decltype(uni_c)::value;
+            // the channel count and the slot pool (the same in every lane:
+            // kernel arguments, or the workgroup's staged request) as scalar
+            // values of this sample: the group tests stay scalar compares and
+            // the pool address stays in registers instead of being hoisted
+            // out of the ray loop
+            // (the builtin returns int: each half is taken back to uint32_t
+            // before widening, so the low half is not sign-extended)
+            int nvs = __builtin_amdgcn_readfirstlane(nvis);
+            const uint64_t pa = reinterpret_cast<uint64_t>(A.slots);
+            const uint32_t phi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(pa >> 32));
+            const uint32_t plo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)pa);
+            uint64_t pv = ((uint64_t)phi << 32) | (uint64_t)plo;
+            asm volatile("" : "+s"(nvs), "+s"(pv));
+            const uint8_t *pool = (const uint8_t *)(const __attribute__((address_space(1))) uint8_t *)pv;
 #pragma unroll
         for (int g = 0; g < NV; g += kGroup) {
-            if (g >= nvis) break;
+            if (g >= nvs) break;
             uint32_t w[kGroup][4];
             float fq[kGroup][3];
             bool ok[kGroup];
 #pragma unroll
             for (int jj = 0; jj < kGroup; ++jj) {
                 const int j = g + jj;
-                ok[jj] = j < nvis && slot[j] != kInvalid;
+                // the slot words of channels past nvis stay invalid
+                ok[jj] = slot[j] != kInvalid;
                 if (rates) ok[jj] = ok[jj] && ((part >> j) & 1u);
                 if constexpr (!UNI) {
                     const int lu = (int)((lvpack >> (4 * j)) & 15u);
@@ -1042,7 +1057,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 fq[jj][2] = fr2;
                 // a channel without a slot reads offset 0 of slot 0 (always
                 // inside the pool) and its result is discarded
-                const uint8_t *base = A.slots + (ok[jj] ? (size_t)slot[j] * stride + (size_t)idx * BPV : 0);
+                const uint8_t *base = pool + (ok[jj] ? (size_t)slot[j] * stride + (size_t)idx * BPV : 0);
                 w[jj][0] = vpair<BPV>(base);
                 w[jj][1] = vpair<BPV>(base + (size_t)E * BPV);
                 w[jj][2] = vpair<BPV>(base + (size_t)E * E * BPV);
