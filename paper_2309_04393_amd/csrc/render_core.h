@@ -72,6 +72,16 @@ struct NodeLds {
 
 __device__ __forceinline__ uint32_t field(uint32_t p, int a) { return (p >> (8 * a)) & 255u; }
 
+// A pointer into device memory, marked as such: accesses through it are
+// global (not flat) memory operations also where the frame's arguments were
+// read from LDS (the serve kernels), where the compiler cannot tell.  The
+// address goes through an integer: a cast to the global address space and
+// straight back would be folded away.
+template <class T>
+__device__ __forceinline__ T *gmem(T *p) {
+    return (T *)(__attribute__((address_space(1))) T *)reinterpret_cast<uintptr_t>(p);
+}
+
 // Zero-alpha runs of a channel's table as raw-value bounds (lo | hi << 16):
 // the range [mn, mx] is empty iff some run has mn >= lo and mx <= hi.  Raw
 // values are at most 65535, so runs whose lower bound exceeds that are
@@ -397,7 +407,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
         }
         Cr = Cg = Cb = 0.0;
         Tr = 1.0;
-        out = valid ? A.rgba + ((size_t)py * A.W + px) * 4 : nullptr;
+        out = valid ? gmem(A.rgba) + ((size_t)py * A.W + px) * 4 : nullptr;
         if (AOV && A.reqb && valid) {
             // required bricks: the count, then each channel's last desired brick
             uint32_t *rb = A.reqb + ((size_t)py * A.W + px) * (1 + nvis);
@@ -454,7 +464,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                     const LevLds lv = s_lv[ls];
                     const int bx = lc[0] >> field(lv.sh, 0), by = lc[1] >> field(lv.sh, 1),
                               bz = lc[2] >> field(lv.sh, 2);
-                    atomicAdd(&A.cnt[brick_dense(lv, (uint32_t)ch.c, A.per_channel, bx, by, bz)], nvisit);
+                    atomicAdd(&gmem(A.cnt)[brick_dense(lv, (uint32_t)ch.c, A.per_channel, bx, by, bz)], nvisit);
                     st_miss += nvisit;
                 }
             }
@@ -641,7 +651,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                                                   iu[2] >> field(nd.nsh, 2));
                     // the node's metadata, kGroup channels per batch of loads
                     uint32_t em = 0, hm = 0;
-                    const uint32_t *nm = A.meta + (size_t)node * m;
+                    const uint32_t *nm = gmem(A.meta) + (size_t)node * m;
                     if (AOV && A.nodes) A.nodes[node] = 1;
 #pragma unroll
                     for (int g = 0; g < NV; g += kGroup) {
@@ -744,7 +754,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                         // wave iteration from here on, without gathers, then
                         // goes on past the node.
                         float hp = 1.0f, hsa = 0.0f, hsr = 0.0f, hsg = 0.0f, hsb = 0.0f;
-                        const uint32_t *rm = A.meta + (size_t)rs_node * m;
+                        const uint32_t *rm = gmem(A.meta) + (size_t)rs_node * m;
                         for (int j = 0; j < nvis; ++j) {
                             if (!((rs_mask >> j) & 1u)) continue;
                             const ChanLds ch = s_ch[j];
@@ -807,7 +817,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
             }
             // Residency masks of the leaf give each channel the level it
             // samples (finest resident at or above the desired one).
-            const uint16_t *lm = A.mask + (size_t)leaf * m;
+            const uint16_t *lm = gmem(A.mask) + (size_t)leaf * m;
             uint32_t look = 0;  // channels with a resident brick to look up
             bool all_at = false;  // every non-empty channel resident at the common desired level
             int lsu = 0;
@@ -902,7 +912,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                             } else {
                                 const int lu = (int)((lvpack >> (4 * j)) & 15u);
                                 const LevLds lv = s_lv[lu];
-                                ns[jj] = A.pt[brick_dense(lv, (uint32_t)s_ch[j].c, A.per_channel,
+                                ns[jj] = gmem(A.pt)[brick_dense(lv, (uint32_t)s_ch[j].c, A.per_channel,
                                                           iu[0] >> field(lv.sh, 0), iu[1] >> field(lv.sh, 1),
                                                           iu[2] >> field(lv.sh, 2))];
                             }
@@ -919,7 +929,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                             if (ns[jj] != slot[j]) {
                                 // with rates the stamp waits for a sample the channel takes part in
                                 if (rates) stamped &= ~(1u << j);
-                                else A.stamp[ns[jj]] = A.frame;
+                                else gmem(A.stamp)[ns[jj]] = A.frame;
                             }
                         }
                         slot[j] = ns[jj];
@@ -948,7 +958,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
                 mp &= mp - 1u;
                 const ChanLds ch = s_ch[j];
                 const LevLds lv = s_lv[min(max(lod, ch.lo), ch.hi)];
-                atomicAdd(&A.cnt[brick_dense(lv, (uint32_t)ch.c, A.per_channel, iu[0] >> field(lv.sh, 0),
+                atomicAdd(&gmem(A.cnt)[brick_dense(lv, (uint32_t)ch.c, A.per_channel, iu[0] >> field(lv.sh, 0),
                                              iu[1] >> field(lv.sh, 1), iu[2] >> field(lv.sh, 2))],
                           1u);
                 ++st_miss;
@@ -957,7 +967,7 @@ __device__ __forceinline__ void render_rays(const RenderArgs &A, Source &src, co
             while (sp) {
                 const int j = __builtin_ctz(sp);
                 sp &= sp - 1u;
-                A.stamp[slot[j]] = A.frame;
+                gmem(A.stamp)[slot[j]] = A.frame;
             }
             stamped |= have & part;
         } else {
