@@ -24,10 +24,11 @@ namespace ro {
 
 // Workgroups of kRenderLanes lanes (768: 3 waves per SIMD, up to 168 VGPRs),
 // one per CU: one copy of the frame's LDS tables plus the per-lane slot
-// words.  The 16-channel instantiations for 32^3 and 16^3 bricks without
-// the options keep nothing in scratch; the other 16-channel ones and some
-// 8-channel ones 8 to 40 bytes per lane.  1024 lanes (4 waves per SIMD, 128 VGPRs) spill
-// more and measured 1-10 % slower, 512 lanes 35 % slower.
+// words.  The 16-channel instantiations for 16-bit 32^3 and 16^3 bricks
+// without the options keep nothing in scratch; the other 16-channel ones up
+// to 40 bytes per lane, three 8-channel ones 12.  1024 lanes (4 waves per
+// SIMD, 128 VGPRs) spill more and measured 1-10 % slower, 512 lanes 35 %
+// slower.
 
 // Lanes refill only when the whole wave is idle: a wave then takes a whole
 // new 8 x 8 block and its rays start together.  Refilling single lanes as
