@@ -16,14 +16,14 @@ from . import resoct
 
 class GpuScene:
     def __init__(self, src, brick: int, leaf, depth: int, n_slots: int, max_batch: int = 4096,
-                 start_level: int = 0, device="cuda", set_metadata=True, cache_channels=None):
+                 start_level: int = 0, device="cuda", set_metadata=True, cache_channels=None, slots=None):
         self.src = src
         self.device = device
         m = src.n_channels if cache_channels is None else int(cache_channels)
         assert 1 <= m <= src.n_channels
         self.vol = resoct.Volume(src.dims, src.spacing, m, 1 if src.bits == 8 else 2,
                                  brick, src.n_levels)
-        self.cache = resoct.Cache(self.vol, n_slots, max_batch, device=device)
+        self.cache = resoct.Cache(self.vol, n_slots, max_batch, device=device, slots=slots)
         self.tree = resoct.Octree(self.cache, leaf, depth, start_level, device=device)
         self.B = brick
         self.E = brick + 2

@@ -217,7 +217,10 @@ class Volume:
 
 
 class Cache:
-    def __init__(self, vol: Volume, n_slots: int, max_batch: int, device="cuda", stream=None):
+    def __init__(self, vol: Volume, n_slots: int, max_batch: int, device="cuda", stream=None, slots=None):
+        """slots: optionally the caller's device buffer for the slot pool (a
+        contiguous uint8 tensor of at least the queried size, 256-byte
+        aligned); the other buffers are allocated here."""
         self.vol = vol
         d = CacheDesc(n_slots, max_batch)
         sz = CacheSizes()
@@ -226,7 +229,15 @@ class Cache:
         self.slot_stride = int(sz.slot_stride)
         self.n_slots, self.max_batch = n_slots, max_batch
         self.t = {name: _alloc(getattr(sz, name), device) for name in
-                  ("slots", "page_table", "counters", "slot_brick", "stamps", "seqs", "scratch")}
+                  ("page_table", "counters", "slot_brick", "stamps", "seqs", "scratch")}
+        if slots is None:
+            self.t["slots"] = _alloc(sz.slots, device)
+        else:
+            if (slots.dtype != torch.uint8 or not slots.is_cuda or not slots.is_contiguous()
+                    or slots.numel() < int(sz.slots) or slots.data_ptr() % 256):
+                raise ValueError(f"slots: a contiguous uint8 device tensor of at least {int(sz.slots)} bytes, "
+                                 "256-byte aligned")
+            self.t["slots"] = slots
         b = CacheBuffers(*[self.t[n].data_ptr() for n in
                            ("slots", "page_table", "counters", "slot_brick", "stamps", "seqs", "scratch")])
         h = c_vp()

@@ -364,3 +364,45 @@ def test_serving_loop_continuous(scene):
         n_exact += _same(img, ref, f"cloop-{r.rid}")
     _report("serve-loop-continuous", requests=len(trace), mean_in_flight=np.mean(loop.in_flight_at_admission),
             bit_exact=f"{n_exact}/{len(trace)}", peak_mb=loop.arena.peak / 2**20, **lat)
+
+
+def test_slot_pool_address_above_2gib_in_low_word(scene):
+    """The slot pool at an address whose low 32-bit half has bit 31 set (the
+    kernels rebuild the pool address from its two halves as scalar values):
+    the frame kernel gives the images of the scene whose pool lies elsewhere,
+    and batches and continuous admission give the frame kernel's images."""
+    src = scene.src
+    n_bricks = scene.cache.n_slots
+    need = int(scene.cache.sizes.slots)
+    pad = torch.empty(need + (1 << 31) + 512, dtype=torch.uint8, device="cuda")
+    base = pad.data_ptr()
+    lo = base & 0xFFFFFFFF
+    off = 0 if lo >= 0x80000000 and lo + need < (1 << 32) else ((0x80000000 - lo) % (1 << 32) + 255) // 256 * 256
+    pool = pad[off:off + need]
+    addr = pool.data_ptr()
+    assert addr % 256 == 0 and (addr & 0xFFFFFFFF) >= 0x80000000
+    print(f"[pool] address {addr:#x} (low half {addr & 0xFFFFFFFF:#010x})", flush=True)
+    s2 = GpuScene(src, 32, (16, 16, 4), 5, n_slots=n_bricks, max_batch=2048, slots=pool)
+    s2.upload(0, s2.all_ids())
+    s2.tree.update_residency()
+    torch.cuda.synchronize()
+    reqs = _requests(src, 60, n=6)
+    ref, _ = Rig(scene, reqs).frame_kernel()
+    rig = Rig(s2, reqs)
+    img, _ = rig.frame_kernel()
+    for k in range(len(reqs)):
+        assert np.isfinite(img[k]).all()
+        assert np.array_equal(img[k], ref[k]), f"frame kernel image {k} differs with the pool at {addr:#x}"
+    srv = resoct.Server(s2.tree, max_requests=8, max_tiles=256)
+    outs = [rig.out(k) for k in range(len(reqs))]
+    torch.cuda.synchronize()
+    srv.wait(srv.launch([rig.fd(k, stats=False) for k in range(len(reqs))], outs))
+    exact = sum(_same(rig.image(k, outs[k]), img[k], f"pool-batch-{k}") for k in range(len(reqs)))
+    outs2 = [rig.out(k) for k in range(len(reqs))]
+    torch.cuda.synchronize()
+    tickets = [srv.enqueue(rig.fd(k, stats=False), outs2[k]) for k in range(len(reqs))]
+    assert None not in tickets
+    _wait_done(srv, tickets)
+    srv.drain()
+    exact += sum(_same(rig.image(k, outs2[k]), img[k], f"pool-cont-{k}") for k in range(len(reqs)))
+    _report("serve-pool-address", address=hex(addr), bit_exact=f"{exact}/{2 * len(reqs)}")
