@@ -40,11 +40,15 @@ namespace ro {
 #define RO_MIN_IDLE 64
 #endif
 
+// Per-XCD block queues: blocks are dealt to them in chunks of RO_CHUNK
+// consecutive blocks (16 chunks per queue at 1080p).  On the 16-channel
+// 1080p frame chunks of 256 measured 0.6 % faster than 64, 16 0.7 % slower,
+// 1024 as 256, and 4096 (one region per XCD) 4 % slower.
 #ifndef RO_QUEUES
 #define RO_QUEUES 8
 #endif
 #ifndef RO_CHUNK
-#define RO_CHUNK 64
+#define RO_CHUNK 256
 #endif
 
 // Persistent grid (one workgroup per CU) whose waves take 8 x 8-pixel blocks
